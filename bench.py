@@ -1,0 +1,237 @@
+"""Benchmark of the matrix-valued quantum lattice Boltzmann step on one GPU.
+
+Default workload: D3Q19, 128^3 periodic cells, tau = 0.8, beta0 = 1, seeded
+smooth Fermi-Dirac initial state (paper_1309_1656_amd.synthetic), K = 500
+steps.  A "step" is one time step of the method (moments, polynomial
+equilibrium, BGK collision, streaming) over the whole lattice; the timed
+region is one mlbm_step(K) call with its inputs resident in device memory.
+
+Printed: one JSON line.  `value` is MLUPS (10^6 cell updates per second) of
+the double-precision step.  Also reported: FP32 and FP16 scaled-deviation
+storage on the same workload, the fused kernel's average duration and HBM
+roofline fraction, the forward + adjoint time of the differentiable rollout
+(D2Q9 512^2, FP32, 200 steps, checkpoints every 20) next to the plain FP64
+forward, a device-copy bandwidth, and the CPU oracle on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+       [--skip-extras] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, AMD published peak
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="d3q19_128")
+    ap.add_argument("--skip-extras", action="store_true", help="only the FP64 headline measurement")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def device_inputs(h, f):
+    import torch
+    rho4 = np.concatenate([f["trrho"][None], f["r"]])
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    return to(rho4), to(h.info["xi"] * f["u_lat"]), to(f["T"])
+
+
+def dims_of(shape):
+    return (shape[1], shape[0], 1) if len(shape) == 2 else (shape[2], shape[1], shape[0])
+
+
+def time_region(fn, reps=1):
+    """Average milliseconds of fn() over reps, by events on the current stream."""
+    import torch
+    s = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        fn()
+    b.record(s)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def measure_step(shape, seed, tau, storage, steps, warmup, f):
+    """MLUPS of mlbm_step(steps) and the fused kernel's average duration."""
+    import torch
+    from paper_1309_1656_amd import mlbm
+    Q = 9 if len(shape) == 2 else 19
+    h = mlbm.mlbm_create(Q, dims_of(shape), tau, 1.0, storage)
+    W = h.empty_field()
+    mlbm.mlbm_init_equilibrium(h, W, *device_inputs(h, f))
+    scratch = h.empty_field()
+    g0, _ = mlbm.mlbm_moments(h, W)
+    if warmup:
+        mlbm.mlbm_step(h, W, scratch, warmup)
+    torch.cuda.synchronize()
+    t_all = time_region(lambda: mlbm.mlbm_step(h, W, scratch, steps))
+    # one collide-only + one stream-only pass: the part of mlbm_step that is not the fused pass
+    t_pair = time_region(lambda: mlbm.mlbm_step(h, W, scratch, 1), reps=5)
+    g1, nneg = mlbm.mlbm_moments(h, W)
+    N = int(np.prod(shape))
+    fused_ms = (t_all - t_pair) / max(steps - 1, 1)
+    bytes_per_cell = 2 * 4 * Q * {0: 8, 1: 4, 2: 2}[storage]
+    achieved = bytes_per_cell * N / (fused_ms * 1e-3) / 1e9
+    drift = float(np.max(np.abs(g1 - g0)) / np.max(np.abs(g0)))
+    out = {
+        "mlups": N * steps / (t_all * 1e-3) / 1e6,
+        "ms_per_step": t_all / steps,
+        "fused_kernel_ms": fused_ms,
+        "fused_kernel_GBps": achieved,
+        "hbm_frac": achieved / HBM_PEAK_GBS,
+        "bytes_per_cell": bytes_per_cell,
+        "global_drift_rel": drift,
+        "n_neg_eig": nneg,
+    }
+    h.destroy()
+    return out
+
+
+def measure_adjoint(warmup):
+    """Forward + adjoint rollout (D2Q9 512^2, FP32, 200 steps, K = 20) vs plain FP64 forward."""
+    import torch
+    from paper_1309_1656_amd import mlbm, synthetic
+    from paper_1309_1656_amd.rollout import MLBMRollout
+    wl = synthetic.WORKLOADS["d2q9_512_adjoint"]
+    shape, steps, tau = wl["shape"], wl["steps"], wl["tau"]
+    f = synthetic.macroscopic_fields(shape, wl["seed"])
+    rt = torch.from_numpy(synthetic.target_bloch_field(shape, wl["seed"] + 100)).cuda()
+    h32 = mlbm.mlbm_create(9, dims_of(shape), tau, 1.0, mlbm.MLBM_STORE_F32)
+    W0 = h32.empty_field()
+    mlbm.mlbm_init_equilibrium(h32, W0, *device_inputs(h32, f))
+    W0.requires_grad_(True)
+    tau_t = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+
+    def fwd_bwd():
+        W0.grad = None
+        tau_t.grad = None
+        loss = MLBMRollout.apply(W0, tau_t, h32, steps, 20, rt)
+        loss.backward()
+        return loss
+
+    for _ in range(max(1, warmup // 10)):
+        fwd_bwd()
+    t_fb = time_region(fwd_bwd)
+    h64 = mlbm.mlbm_create(9, dims_of(shape), tau, 1.0, mlbm.MLBM_STORE_F64)
+    W64 = h64.empty_field()
+    mlbm.mlbm_init_equilibrium(h64, W64, *device_inputs(h64, f))
+    s64 = h64.empty_field()
+    mlbm.mlbm_step(h64, W64, s64, 20)
+    t_f64 = time_region(lambda: mlbm.mlbm_step(h64, W64, s64, steps))
+    return {"workload": "d2q9_512^2_f32_200steps_ckpt20", "fwd_adjoint_ms": t_fb,
+            "plain_f64_forward_ms": t_f64, "ratio_to_f64_forward": t_fb / t_f64,
+            "grad_tau": float(tau_t.grad), "grad_W0_norm": float(W0.grad.norm())}
+
+
+def copy_bandwidth():
+    import torch
+    n = 1 << 28   # 2 GiB of float64 each way
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    ms = time_region(lambda: b.copy_(a), reps=5)
+    del a, b
+    return 2 * n * 8 / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(seconds=12.0):
+    """The FP64 oracle on a bounded sample: D3Q19 48^3 cells, steps until ~seconds."""
+    from oracle import qlbm
+    from paper_1309_1656_amd import synthetic
+    shape = (48, 48, 48)
+    lat = qlbm.Lattice(3)
+    f = synthetic.macroscopic_fields(shape, synthetic.BASE_SEED + 3)
+    W = qlbm.init_equilibrium(lat, f["trrho"], f["r"], lat.xi * f["u_lat"], f["T"])
+    W = qlbm.step(lat, W, 0.8)           # warm-up
+    n, t0 = 0, time.perf_counter()
+    while n < 3 or time.perf_counter() - t0 < seconds:
+        W = qlbm.step(lat, W, 0.8)
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": int(np.prod(shape)) * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"D3Q19 48^3 cells, {n} steps, tau 0.8, same initial-state family as the workload",
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the design for spatial sharding is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1309_1656_amd import mlbm, synthetic
+    torch.cuda.set_device(0)
+    mlbm.load_library()
+    wl = synthetic.WORKLOADS[args.workload]
+    shape, tau = wl["shape"], wl["tau"]
+    log(f"workload {args.workload} {shape} tau={tau}: generating inputs")
+    f = synthetic.macroscopic_fields(shape, wl["seed"])
+    log("FP64 step")
+    r64 = measure_step(shape, wl["seed"], tau, mlbm.MLBM_STORE_F64, args.steps, args.warmup, f)
+    log(f"  {r64['mlups']:.0f} MLUPS, fused {r64['fused_kernel_ms']:.4f} ms, {r64['fused_kernel_GBps']:.0f} GB/s")
+    extras = {}
+    if not args.skip_extras:
+        for name, st in (("fp32", mlbm.MLBM_STORE_F32), ("f16dev", mlbm.MLBM_STORE_F16DEV)):
+            log(f"{name} step")
+            extras[name] = measure_step(shape, wl["seed"], tau, st, args.steps, args.warmup, f)
+            log(f"  {extras[name]['mlups']:.0f} MLUPS, {extras[name]['fused_kernel_GBps']:.0f} GB/s")
+        log("forward + adjoint rollout")
+        extras["adjoint"] = measure_adjoint(args.warmup)
+        log(f"  ratio {extras['adjoint']['ratio_to_f64_forward']:.2f}")
+        extras["copy_GBps"] = copy_bandwidth()
+        log(f"copy {extras['copy_GBps']:.0f} GB/s")
+    Q = 9 if len(shape) == 2 else 19
+    grid = "x".join(str(s) for s in reversed(shape))
+    line = {
+        "metric": "MLUPS & HBM-roofline fraction, D3Q19 step: FP32 vs FP64, fwd+adjoint time",
+        "value": r64["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{'D2Q9' if Q == 9 else 'D3Q19'} {grid} periodic, tau {tau}, beta0 1, "
+                               f"smooth Fermi-Dirac initial state, FP64 storage",
+                   "lattice": "D2Q9" if Q == 9 else "D3Q19", "grid": list(reversed(shape)), "tau": tau},
+        "roofline": {"bound": "hbm", "achieved": r64["fused_kernel_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r64["fused_kernel_GBps"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_step<19, F64, pull, collide>", "kernel_ms": r64["fused_kernel_ms"],
+                     "bytes_per_cell": r64["bytes_per_cell"]},
+        "f64": r64,
+    }
+    line.update(extras)
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline()
+        log(f"  {line['cpu_baseline']['value']:.3f} MLUPS")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,268 @@
+/*
+ * mlbm.h -- C ABI of the matrix-valued quantum lattice Boltzmann library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method is Mendl, "Matrix-valued Quantum Lattice Boltzmann Method"
+ * (arXiv:1309.1656), Sec. 3.  Every population W_i(x) is a 2x2 complex
+ * Hermitian spin-density matrix (Sec. 2, after Eq. BoltzmannEquation), held
+ * here as four real Pauli coefficients
+ *     W = (a0 I + a1 sigma_x + a2 sigma_y + a3 sigma_z) / 2,
+ * so a0 = tr W and ak = tr(W sigma_k) (the Bloch components of Sec. 4).
+ *
+ * ---------------------------------------------------------------------------
+ * Lattices and velocity order (Sec. 3, Fig. 1; Sec. 3.1).  e_i = xi * c_i.
+ *   D2Q9  (Q = 9):  0:(0,0)  1:(1,0) 2:(-1,0) 3:(0,1) 4:(0,-1)
+ *                   5:(1,1) 6:(-1,-1) 7:(1,-1) 8:(-1,1)
+ *   D3Q19 (Q = 19): 0:(0,0,0)
+ *                   1:(1,0,0) 2:(-1,0,0) 3:(0,1,0) 4:(0,-1,0) 5:(0,0,1) 6:(0,0,-1)
+ *                   7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0)
+ *                   11:(1,0,1) 12:(-1,0,-1) 13:(1,0,-1) 14:(-1,0,1)
+ *                   15:(0,1,1) 16:(0,-1,-1) 17:(0,1,-1) 18:(0,-1,1)
+ *   Components are (x, y[, z]).  Weights: D2Q9 {1-5a, a, a/4}, D3Q19
+ *   {1-12a, a, a/2} by number of nonzero components (Eqs. QuadSolution2D/3D at
+ *   mu0 = 0, Eqs. QuadSolution2Dmu0 / QuadSolution3Dmu0).
+ *
+ * Field layout ("a field").  Structure of arrays, one contiguous plane of N
+ * cells per (Pauli component k, velocity i):
+ *     element (k, i, cell) at offset ((k * Q) + i) * N + cell,
+ *     cell = x + nx * (y + ny * z),  N = nx * ny * nz,
+ * i.e. a C-contiguous array [4][Q][nz][ny][nx] of the storage type.  Periodic
+ * boundaries in every direction (Sec. 3).  Storage types:
+ *   MLBM_STORE_F64     double; all arithmetic in double.
+ *   MLBM_STORE_F32     float; collision arithmetic in float, moment sums in
+ *                      double.
+ *   MLBM_STORE_F16DEV  IEEE binary16 h = (a - R_ki) / (w_i S), the scaled
+ *                      deviation from a lattice-weighted reference
+ *                      equilibrium R_ki = w_i rho_bar_k P_i(u_bar, eps_bar) of
+ *                      the global means of the initial state, with a global
+ *                      power-of-two scale S; both are fixed by
+ *                      mlbm_init_equilibrium and kept in the handle.  Encoding
+ *                      rounds to nearest even; arithmetic in float, moment sums
+ *                      in double.
+ *
+ * Time stepping (Sec. 3.3): Delta t = 1, Delta x = xi, omega = 1/tau.  One step
+ * computes per cell the moments rho, u, eps (Eq. DiscrAvr), the polynomial
+ * equilibrium W_eq_i = w_i rho P_i(u, eps) (Eq. WeqAlgo, Appendix
+ * coefficients with eps_FD = eps), the BGK collision (Eq. CollisionStep) and
+ * the periodic streaming W_i(x + c_i) <- W_coll_i(x) (Eq. TransportStep).
+ *
+ * Memory ownership.  Every field and every per-cell array passed to the
+ * library is caller-owned DEVICE memory (for instance a torch tensor),
+ * contiguous, aligned to at least 16 bytes, on the current HIP device.  The
+ * handle owns only its constants, the F16DEV reference and scale, and a small
+ * private device buffer for reductions and status flags (allocated on first
+ * use).  Pointers documented as "host" are ordinary host memory.
+ *
+ * Streams.  Every call that takes `stream` (a hipStream_t; NULL means the
+ * null stream) enqueues its work asynchronously on that stream and returns.
+ * The exceptions synchronise `stream` and say so: mlbm_init_equilibrium
+ * (reads back status flags) and mlbm_moments when a host output is requested.
+ * A handle must not be used by two host threads at once; calls on one handle
+ * on different streams must be ordered by the caller.
+ *
+ * Errors.  Every call returns MLBM_OK (0) or a negative status.  When argument
+ * validation fails nothing is enqueued.  mlbm_last_error() returns a message
+ * describing the last failure on the calling thread.
+ */
+#ifndef MLBM_H
+#define MLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mlbm_ctx* mlbm_handle;
+
+enum { MLBM_D2Q9 = 9, MLBM_D3Q19 = 19 };
+enum { MLBM_STORE_F64 = 0, MLBM_STORE_F32 = 1, MLBM_STORE_F16DEV = 2 };
+enum { MLBM_EQ_DIRECT = 0, MLBM_EQ_EIGEN = 1 };
+enum {
+    MLBM_OK = 0,
+    MLBM_EINVAL = -1,     /* bad argument: null pointer, bad enum, bad size   */
+    MLBM_EDOMAIN = -2,    /* outside the method's domain (tau <= 1/2, ...)   */
+    MLBM_EHIP = -3,       /* HIP runtime failure; message has hipGetErrorString */
+    MLBM_ENOMEM = -4,     /* device allocation of the private buffer failed   */
+    MLBM_ENONFINITE = -5, /* a NaN or infinity was found in a field           */
+    MLBM_ENOCONV = -6     /* a Fermi-Dirac parameter inversion did not converge */
+};
+
+/* Read-only description of a handle (mlbm_get_info). */
+typedef struct {
+    int lattice;          /* MLBM_D2Q9 or MLBM_D3Q19 (= Q)                    */
+    int d;                /* 2 or 3                                           */
+    int storage;          /* MLBM_STORE_*                                      */
+    int eq_mode;          /* MLBM_EQ_*                                         */
+    int64_t nx, ny, nz;   /* grid; nz = 1 for D2Q9                             */
+    int64_t ncell;        /* N = nx * ny * nz                                  */
+    double tau, omega;    /* relaxation time and omega = Delta t / tau         */
+    double beta0;         /* reference inverse temperature of the cubature    */
+    double xi;            /* lattice constant = lattice speed, xi1 / sqrt(beta0) */
+    double a;             /* cubature weight parameter at mu0 = 0              */
+    double w[19];         /* weight of velocity i (first Q entries used)       */
+    int c[19][3];         /* integer velocity c_i (x, y, z)                    */
+    /* Appendix coefficients: alpha1 = a1_0 + a1_b b, alpha2 = a2_0 + a2_b b,
+     * b = beta0 eps; alpha3..alpha5 constant.                                 */
+    double a1_0, a1_b, a2_0, a2_b, a3, a4, a5;
+    double f16_scale;     /* S of MLBM_STORE_F16DEV (0 before initialisation) */
+    double f16_ref[4][19];/* R_ki of MLBM_STORE_F16DEV                          */
+} mlbm_info;
+
+/*
+ * mlbm_create -- set up a lattice of dims = {nx, ny, nz} cells (nz = 1 for
+ * D2Q9), relaxation time tau (Eq. C_BGK, Eq. CollisionStep) and reference
+ * inverse temperature beta0 of the cubature (Sec. 3.3, first paragraph;
+ * mu0 = 0).  Computes xi, w_i and the Appendix coefficients in double on the
+ * host.  Touches no device memory.
+ *   lattice  MLBM_D2Q9 or MLBM_D3Q19.   storage  MLBM_STORE_*.
+ *   Each dim >= 1 and N < 2^31.
+ * Errors: MLBM_EINVAL (null out/dims, bad lattice/storage/dims),
+ *         MLBM_EDOMAIN (tau <= 1/2 or not finite, beta0 <= 0 or not finite).
+ *         tau > 1/2 keeps |1 - omega| < 1.
+ * On success *out holds a new handle; release it with mlbm_destroy.
+ */
+int mlbm_create(mlbm_handle* out, int lattice, const int64_t dims[3],
+                double tau, double beta0, int storage);
+
+/* mlbm_destroy -- free the handle and its private device buffer (NULL is a no-op). */
+void mlbm_destroy(mlbm_handle h);
+
+/* mlbm_get_info -- copy the handle's parameters into *info (host). */
+int mlbm_get_info(mlbm_handle h, mlbm_info* info);
+
+/* mlbm_field_bytes -- bytes of one field: 4 * Q * N * sizeof(storage type). */
+int mlbm_field_bytes(mlbm_handle h, size_t* bytes);
+
+/* mlbm_set_tau -- change the relaxation time (same rules as mlbm_create). */
+int mlbm_set_tau(mlbm_handle h, double tau);
+
+/*
+ * mlbm_set_eq_mode -- choose how the collision builds W_eq.
+ *   MLBM_EQ_DIRECT (default): Eq. WeqAlgo, W_eq_i = w_i rho P_i(u, eps); no U,
+ *     no Fermi-Dirac integral (Sec. 3.3, first item).
+ *   MLBM_EQ_EIGEN: Eq. WeqDiscr taken literally: per cell the closed-form
+ *     eigen-decomposition of rho gives U and the channel densities, a
+ *     double-precision Newton inversion gives (beta, nu_up, nu_dn) with those
+ *     densities and internal energy eps (Prop. 1), and
+ *     W_eq_i = w_i U diag(n_up, n_dn) U* P_i(u, eps_FD) is rebuilt from them.
+ *     Equal to the direct form up to the inversion tolerance; a checking mode,
+ *     many times slower.  Only for MLBM_STORE_F64 (else MLBM_EINVAL).
+ */
+int mlbm_set_eq_mode(mlbm_handle h, int mode);
+
+/*
+ * mlbm_init_equilibrium -- write into field W the discrete Fermi-Dirac
+ * equilibrium of per-cell macroscopic data (Eq. WeqDiscr; Eqs. WFermiDirac,
+ * nFDstdOmega, energyFDstdOmega):
+ *   rho4 [4][N] double (device): tr rho, r_x, r_y, r_z, where r is the Bloch
+ *        vector r_k = tr(rho sigma_k), so rho = (tr rho I + r . sigma) / 2;
+ *   u    [d][N] double (device): velocity in momentum units (the lattice speed
+ *        is xi);
+ *   T    [N]    double (device): temperature 1 / beta.
+ * Per cell the channel densities n_up/dn = (tr rho +- |r|)/2 are inverted to
+ * nu = beta mu by n = (2 pi / beta)^(d/2) F_{d/2-1}(nu) (closed form for d = 2,
+ * Newton in double for d = 3), eps = (d/2) T sum F_{d/2}(nu) / sum F_{d/2-1}(nu),
+ * and W_i = w_i rho P_i(u, eps).  For MLBM_STORE_F16DEV the routine first
+ * reduces the global means and the maximal deviation to fix R and S.
+ * Synchronises `stream` (reads back status flags).
+ * Errors: MLBM_EINVAL (null pointers), MLBM_EDOMAIN (some cell has tr rho <= 0,
+ * |r| >= tr rho, T <= 0, or a non-finite input), MLBM_ENOCONV (Newton failed),
+ * MLBM_EHIP.  After a device-side EDOMAIN / ENOCONV the content of W is
+ * unspecified.
+ */
+int mlbm_init_equilibrium(mlbm_handle h, void* W, const double* rho4,
+                          const double* u, const double* T, void* stream);
+
+/*
+ * mlbm_step -- advance W by nsteps >= 0 time steps (Sec. 3.3).  W holds the
+ * pre-collision state W(t) on entry and W(t + nsteps) on exit.  `scratch` is a
+ * second field of the same size, distinct from W, clobbered.  Implementation:
+ * one collide-only pass, nsteps - 1 fused pull-stream + collide passes, one
+ * stream-only pass, ping-ponging between W and scratch so that no copy is made.
+ * Errors: MLBM_EINVAL (null or equal pointers, nsteps < 0), MLBM_EHIP.
+ */
+int mlbm_step(mlbm_handle h, void* W, void* scratch, int nsteps, void* stream);
+
+/*
+ * mlbm_collide -- dst = C(src), the BGK collision of Eq. CollisionStep cell
+ * by cell, no streaming.  dst may equal src (in place).
+ */
+int mlbm_collide(mlbm_handle h, const void* src, void* dst, void* stream);
+
+/*
+ * mlbm_stream -- dst_i(x) = src_i(x - c_i), the periodic transport of
+ * Eq. TransportStep alone.  A pure permutation of the stored values (bit
+ * exact in every storage type).  dst must not overlap src.
+ */
+int mlbm_stream(mlbm_handle h, const void* src, void* dst, void* stream);
+
+/*
+ * mlbm_moments -- per-cell and global moments of a field W (Eq. DiscrAvr;
+ * Eqs. GlobalDensity, GlobalVelocity, GlobalTotalEnergy).  Each output may be
+ * NULL.
+ *   rho4 [4][N] double (device): Pauli coefficients of rho = sum_i W_i;
+ *   u    [d][N] double (device): velocity, tr(rho) u = sum_i e_i tr W_i;
+ *   eps  [N]    double (device): internal energy,
+ *        tr(rho) eps = sum_i |e_i - u|^2/2 tr W_i;
+ *   global8 [8] double (host): cell averages of the 4 Pauli coefficients of
+ *        rho, of tr(rho) u (3 entries, third 0 in 2D) and of
+ *        tr(rho)(eps + |u|^2/2) = sum_i |e_i|^2/2 tr W_i;
+ *   n_neg_eig [1] int64 (host): number of populations W_i(x) with a negative
+ *        eigenvalue (a0 - |a| < 0; Sec. 3.2, last paragraph; Sec. 3.3).
+ * Global sums are reduced in a fixed order (bitwise reproducible).  When a host
+ * output is requested the call synchronises `stream`, and returns
+ * MLBM_ENONFINITE (outputs still written) if any value of W is NaN or infinite.
+ */
+int mlbm_moments(mlbm_handle h, const void* W, double* rho4, double* u,
+                 double* eps, double* global8, int64_t* n_neg_eig, void* stream);
+
+/*
+ * mlbm_spin_loss -- L = (1/N) sum_x |r(x) - r_target(x)|^2 with r the Bloch
+ * vector of rho(x) = sum_i W_i(x), and its gradient with respect to W:
+ *   r_target [3][N] double (device);
+ *   loss     device double, overwritten with L (may be NULL);
+ *   lam      device field of W's storage type (may be NULL): component k of
+ *            every population set to dL/da_k = (2/N)(r_k - r_target_k) for
+ *            k = 1..3 and to 0 for k = 0.
+ * MLBM_STORE_F16DEV is rejected (MLBM_EINVAL).
+ */
+int mlbm_spin_loss(mlbm_handle h, const void* W, const double* r_target,
+                   double* loss, void* lam, void* stream);
+
+/*
+ * mlbm_adjoint_step -- reverse-mode derivative of one step W_{n+1} =
+ * S(C(W_n)) (Eqs. CollisionStep, TransportStep):
+ *   W_n       field, the pre-collision state of step n (device);
+ *   lam_next  field, dL/da of W_{n+1} (device);
+ *   lam_n     field, written with dL/da of W_n (device; must not overlap the
+ *             inputs);
+ *   dL_domega device double: the step's partial derivative with respect to
+ *             omega = 1/tau is ADDED to it (dL/dtau = -dL/domega / tau^2).
+ * Derivative, with g_i(x) = lam_next_i(x + c_i) and G_i = w_i sum_k g_ik rho_k:
+ *   lam_n_jk = (1-omega) g_jk + omega sum_i w_i P_i g_ik
+ *              + [k = 0] omega (G_u.(e_j - u) + G_eps(|e_j - u|^2/2 - eps)) / tr rho,
+ *   G_u = sum_i G_i dP_i/du,  G_eps = sum_i G_i dP_i/deps,
+ *   dL/domega += sum_{x,i,k} g_ik (W_eq_ik - a_ik).
+ * Storage MLBM_STORE_F64 or MLBM_STORE_F32 (float fields, double sums);
+ * MLBM_STORE_F16DEV and MLBM_EQ_EIGEN are rejected (MLBM_EINVAL).
+ */
+int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next,
+                      void* lam_n, double* dL_domega, void* stream);
+
+/*
+ * mlbm_set_f16_reference -- restore the MLBM_STORE_F16DEV reference R (4*Q
+ * doubles, [k][i], host) and scale S > 0 saved from mlbm_get_info, so that a
+ * saved F16DEV field can be resumed on a new handle.
+ */
+int mlbm_set_f16_reference(mlbm_handle h, const double* ref, double scale);
+
+/* mlbm_last_error -- message of the last failed call on this thread ("" if none). */
+const char* mlbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLBM_H */

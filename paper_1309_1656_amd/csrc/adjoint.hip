@@ -1,0 +1,188 @@
+// Reverse-mode derivative of one step W_{n+1} = S(C(W_n)) (Eqs. CollisionStep,
+// TransportStep), derived from Sec. 3.3.
+//
+// With g_i(x) = lam_{n+1,i}(x + c_i) (transpose of the streaming
+// permutation), rho_k = sum_i a_ik, wP_i = w_i P_i and G_i = w_i sum_k g_ik rho_k:
+//   lam_n_jk = (1 - omega) g_jk + omega sum_i wP_i g_ik
+//              + [k = 0] omega (G_u . (e_j - u) + G_eps (|e_j - u|^2/2 - eps)) / T,
+//   G_u  = sum_i G_i dP_i/du,   dP_i/du  = beta0 xi c_i (alpha3 + 2 alpha4 c_i.v) + alpha5 beta0 u,
+//   G_eps = sum_i G_i dP_i/deps, dP_i/deps = beta0 (a1_b + a2_b beta0 xi^2 |c_i|^2 / 2),
+//   dL/domega += sum_{i,k} g_ik (wP_i rho_k - a_ik),
+// where v = beta0 xi u, and du/d(tr W_j) = (e_j - u)/T,
+// deps/d(tr W_j) = (|e_j - u|^2/2 - eps)/T.
+//
+// One thread per cell; fields are read in the storage type and all
+// arithmetic is in double.  The trace channel is handled first and last so
+// that each Bloch channel k = 1..3 is loaded, used and written in turn.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace mlbm {
+
+// Periodic neighbour coordinates of a push: index [c + 1] holds (x + c) mod n.
+__device__ __forceinline__ void push_coords(int x, int n, int stride, int out[3]) {
+    out[0] = ((x == 0) ? n - 1 : x - 1) * stride;
+    out[1] = x * stride;
+    out[2] = ((x + 1 == n) ? 0 : x + 1) * stride;
+}
+
+template <int Q, int MODE>
+__global__ void __launch_bounds__(256)
+k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<MODE>::T* __restrict__ ln1,
+          typename Store<MODE>::T* __restrict__ ln, const KParams p, double* __restrict__ partials) {
+    using T = typename Store<MODE>::T;
+    constexpr int D = Lat<Q>::D;
+    __shared__ double sh[256];
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    double dom = 0.0;
+    if (x < p.nx && y < p.ny) {
+        const int nxy = p.nx * p.ny;
+        const int node = x + p.nx * y + nxy * z;
+        const size_t N = static_cast<size_t>(p.ncell);
+        int sn[Q];
+        {
+            int xo[3], yo[3], zo[3];
+            push_coords(x, p.nx, 1, xo);
+            push_coords(y, p.ny, p.nx, yo);
+            if constexpr (D == 3) push_coords(z, p.nz, nxy, zo);
+            else zo[0] = zo[1] = zo[2] = 0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                sn[i] = xo[Lat<Q>::c(i, 0) + 1] + yo[Lat<Q>::c(i, 1) + 1] + zo[Lat<Q>::c(i, 2) + 1];
+        }
+        // trace channel of W_n: moments and the polynomial factor
+        double a0[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) a0[i] = static_cast<double>(Wn[i * N + node]);
+        double Tr = 0.0, J[3] = {0.0, 0.0, 0.0}, K = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            Tr += a0[i];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) J[c] += Lat<Q>::c(i, c) * a0[i];
+            K += csq<Q>(i) * a0[i];
+        }
+        const double invT = 1.0 / Tr;
+        double u[3], uu = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            u[c] = (c < D) ? p.xi * J[c] * invT : 0.0;
+            uu += u[c] * u[c];
+        }
+        const double eps = p.half_xi2 * K * invT - 0.5 * uu;
+        const double b = p.beta0 * eps;
+        const double A = p.a1_0 + p.a1_b * b + p.a5 * p.beta0 * 0.5 * uu;
+        const double B = (p.a2_0 + p.a2_b * b) * p.beta0 * p.half_xi2;
+        const double bx = p.beta0 * p.xi;
+        double wP[Q], cv[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            cv[i] = bx * (Lat<Q>::c(i, 0) * u[0] + Lat<Q>::c(i, 1) * u[1] + Lat<Q>::c(i, 2) * u[2]);
+            wP[i] = p.w[i] * (A + B * csq<Q>(i) + cv[i] * (p.a3 + p.a4 * cv[i]));
+        }
+        const double om = p.om, omm = p.one_m_om;
+        // trace channel of lam_{n+1}, gathered from x + c_i
+        double g0[Q], G[Q];
+        double h0 = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            g0[i] = static_cast<double>(ln1[i * N + sn[i]]);
+            h0 += g0[i] * wP[i];
+            dom += g0[i] * (wP[i] * Tr - a0[i]);
+            G[i] = p.w[i] * g0[i] * Tr;
+        }
+        // Bloch channels
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            double ak[Q], gk[Q];
+            double rk = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                ak[i] = static_cast<double>(Wn[(k * Q + i) * N + node]);
+                rk += ak[i];
+            }
+            double hk = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                gk[i] = static_cast<double>(ln1[(k * Q + i) * N + sn[i]]);
+                hk += gk[i] * wP[i];
+                dom += gk[i] * (wP[i] * rk - ak[i]);
+                G[i] += p.w[i] * gk[i] * rk;
+            }
+            const double mix = om * hk;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) ln[(k * Q + i) * N + node] = static_cast<T>(omm * gk[i] + mix);
+        }
+        // G_u, G_eps and the trace-channel output
+        double Gu[3] = {0.0, 0.0, 0.0}, Gsum = 0.0, Ge = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double f = G[i] * bx * (p.a3 + 2.0 * p.a4 * cv[i]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Gu[c] += Lat<Q>::c(i, c) * f;
+            Gsum += G[i];
+            Ge += G[i] * (p.a1_b + p.a2_b * p.beta0 * p.half_xi2 * csq<Q>(i));
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Gu[c] += p.a5 * p.beta0 * u[c] * Gsum;
+        Ge *= p.beta0;
+        const double mix0 = om * h0;
+        const double sc = om * invT;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            double gdu = 0.0, dev2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double dv = p.xi * Lat<Q>::c(j, c) - u[c];
+                gdu += Gu[c] * dv;
+                dev2 += dv * dv;
+            }
+            ln[j * N + node] = static_cast<T>(omm * g0[j] + mix0 + sc * (gdu + Ge * (0.5 * dev2 - eps)));
+        }
+    }
+    // block partial of dL/domega (fixed tree: reproducible)
+    sh[tid] = dom;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) sh[tid] += sh[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        partials[bid] = sh[0];
+    }
+}
+
+static dim3 adj_block(int nx) {
+    int bx = nx >= 256 ? 256 : (nx >= 128 ? 128 : 64);
+    return dim3(bx, 256 / bx, 1);
+}
+
+int adjoint_blocks(int nx, int ny, int nz) {
+    dim3 blk = adj_block(nx);
+    return ((nx + blk.x - 1) / blk.x) * ((ny + blk.y - 1) / blk.y) * nz;
+}
+
+template <int Q, int MODE>
+static hipError_t adj_q(const void* Wn, const void* l1, void* l0, const KParams& p, double* partials,
+                        hipStream_t s) {
+    using T = typename Store<MODE>::T;
+    dim3 blk = adj_block(p.nx);
+    dim3 grd((p.nx + blk.x - 1) / blk.x, (p.ny + blk.y - 1) / blk.y, p.nz);
+    hipLaunchKernelGGL((k_adjoint<Q, MODE>), grd, blk, 0, s, static_cast<const T*>(Wn), static_cast<const T*>(l1),
+                       static_cast<T*>(l0), p, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(int Q, int mode, const void* Wn, const void* lam_next, void* lam_n,
+                          const KParams& p, double* partials, hipStream_t s) {
+    if (Q == 9) return mode == kF64 ? adj_q<9, kF64>(Wn, lam_next, lam_n, p, partials, s)
+                                    : adj_q<9, kF32>(Wn, lam_next, lam_n, p, partials, s);
+    return mode == kF64 ? adj_q<19, kF64>(Wn, lam_next, lam_n, p, partials, s)
+                        : adj_q<19, kF32>(Wn, lam_next, lam_n, p, partials, s);
+}
+
+}  // namespace mlbm

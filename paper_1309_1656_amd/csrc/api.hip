@@ -1,0 +1,428 @@
+// C ABI of the library (declared and documented in include/mlbm.h).
+//
+// Host-side work only: argument validation, constants, launch sequencing,
+// the private reduction buffer and status codes.  Every numerical step runs
+// in the kernels of step.hip, moments.hip, init.hip, adjoint.hip, eigen.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "constants.hpp"
+#include "internal.hpp"
+#include "mlbm.h"
+
+using namespace mlbm;
+
+struct mlbm_ctx {
+    int Q = 0, d = 0, storage = 0, eq_mode = MLBM_EQ_DIRECT;
+    int64_t nx = 0, ny = 0, nz = 0, N = 0;
+    double tau = 0.0, beta0 = 0.0;
+    HostConst hc{};
+    KParams kp{};
+    FdParams fp{};
+    double f16_scale = 0.0;
+    double f16_ref[4][19] = {};
+    int device = -1;
+    double* d_partials = nullptr;   // reduction partials
+    size_t partials_cap = 0;        // in doubles
+    double* d_result = nullptr;     // kRedSlots finalised values
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() {
+    g_err.clear();
+    return MLBM_OK;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(MLBM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+int elem_size(int storage) { return storage == MLBM_STORE_F64 ? 8 : (storage == MLBM_STORE_F32 ? 4 : 2); }
+
+int check_handle(mlbm_handle h) {
+    if (!h) return fail(MLBM_EINVAL, "null handle");
+    return MLBM_OK;
+}
+
+// Relaxation parameters into the kernel block.
+void set_tau(mlbm_ctx* h, double tau) {
+    h->tau = tau;
+    KParams& p = h->kp;
+    p.om = 1.0 / tau;
+    p.one_m_om = 1.0 - p.om;
+    p.one_m_omf = static_cast<float>(p.one_m_om);
+    for (int i = 0; i < h->Q; ++i) {
+        p.omw[i] = p.om * p.w[i];
+        p.omwf[i] = static_cast<float>(p.omw[i]);
+    }
+}
+
+void set_f16(mlbm_ctx* h, const double* ref, double scale) {
+    h->f16_scale = scale;
+    for (int k = 0; k < 4; ++k)
+        for (int i = 0; i < h->Q; ++i) {
+            h->f16_ref[k][i] = ref[k * h->Q + i];
+            h->kp.ref[k][i] = static_cast<float>(ref[k * h->Q + i]);
+        }
+    for (int i = 0; i < h->Q; ++i) {
+        h->kp.wS[i] = static_cast<float>(h->kp.w[i] * scale);
+        h->kp.inv_wS[i] = static_cast<float>(1.0 / (h->kp.w[i] * scale));
+    }
+}
+
+// Private device buffer: at least `need` doubles of partials plus the result row.
+int ensure_scratch(mlbm_ctx* h, size_t need) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (h->device >= 0 && dev != h->device)
+        return fail(MLBM_EINVAL, "handle first used on device %d, now called on device %d", h->device, dev);
+    if (h->d_partials && h->partials_cap >= need) return MLBM_OK;
+    if (h->d_partials) {
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipFree(h->d_partials));
+        h->d_partials = nullptr;
+    }
+    if (!h->d_result) {
+        if (hipMalloc(&h->d_result, kRedSlots * sizeof(double)) != hipSuccess)
+            return fail(MLBM_ENOMEM, "cannot allocate %zu bytes of device memory", kRedSlots * sizeof(double));
+    }
+    if (hipMalloc(&h->d_partials, need * sizeof(double)) != hipSuccess) {
+        h->d_partials = nullptr;
+        return fail(MLBM_ENOMEM, "cannot allocate %zu bytes of device memory", need * sizeof(double));
+    }
+    h->partials_cap = need;
+    h->device = dev;
+    return MLBM_OK;
+}
+
+int red_scratch(mlbm_ctx* h) { return ensure_scratch(h, static_cast<size_t>(kRedBlocks) * kRedSlots); }
+
+// Host copy of the polynomial factor P_i (Eq. WeqAlgo) for the F16DEV reference.
+double host_P(const mlbm_ctx* h, int i, const double u[3], double eps) {
+    const KParams& p = h->kp;
+    const double b = p.beta0 * eps;
+    double eu = 0.0, uu = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        eu += p.xi * (h->Q == 9 ? Lat<9>::c(i, c) : Lat<19>::c(i, c)) * u[c];
+        uu += u[c] * u[c];
+    }
+    const int c2 = h->Q == 9 ? csq<9>(i) : csq<19>(i);
+    return p.a1_0 + p.a1_b * b + (p.a2_0 + p.a2_b * b) * p.beta0 * p.half_xi2 * c2 + p.a3 * p.beta0 * eu +
+           p.a4 * (p.beta0 * eu) * (p.beta0 * eu) + p.a5 * p.beta0 * 0.5 * uu;
+}
+
+int read_result(mlbm_ctx* h, double out[kRedSlots], hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(out, h->d_result, kRedSlots * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MLBM_OK;
+}
+
+int check_init_flags(const double r[kRedSlots]) {
+    if (r[8] > 0) return fail(MLBM_EDOMAIN, "%.0f cells outside the Fermi-Dirac domain "
+                                            "(need tr rho > 0, |r| < tr rho, T > 0, finite values)", r[8]);
+    if (r[9] > 0) return fail(MLBM_ENOCONV, "Fermi-Dirac inversion failed in %.0f cells", r[9]);
+    return MLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mlbm_last_error(void) { return g_err.c_str(); }
+
+int mlbm_create(mlbm_handle* out, int lattice, const int64_t dims[3], double tau, double beta0, int storage) {
+    if (!out || !dims) return fail(MLBM_EINVAL, "null argument");
+    *out = nullptr;
+    if (lattice != MLBM_D2Q9 && lattice != MLBM_D3Q19) return fail(MLBM_EINVAL, "lattice must be 9 or 19");
+    if (storage < MLBM_STORE_F64 || storage > MLBM_STORE_F16DEV) return fail(MLBM_EINVAL, "bad storage type");
+    if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return fail(MLBM_EINVAL, "dims must be >= 1");
+    if (lattice == MLBM_D2Q9 && dims[2] != 1) return fail(MLBM_EINVAL, "D2Q9 needs nz = 1");
+    if (dims[1] > 65535 || dims[2] > 65535) return fail(MLBM_EINVAL, "ny and nz must be <= 65535");
+    const long double n = static_cast<long double>(dims[0]) * dims[1] * dims[2];
+    if (n >= 2147483648.0L) return fail(MLBM_EINVAL, "at most 2^31 - 1 cells");
+    if (!(std::isfinite(tau) && tau > 0.5)) return fail(MLBM_EDOMAIN, "tau must be finite and > 1/2 (got %g)", tau);
+    if (!(std::isfinite(beta0) && beta0 > 0.0)) return fail(MLBM_EDOMAIN, "beta0 must be finite and > 0 (got %g)", beta0);
+
+    mlbm_ctx* h = new mlbm_ctx();
+    h->Q = lattice;
+    h->d = lattice == MLBM_D2Q9 ? 2 : 3;
+    h->storage = storage;
+    h->nx = dims[0];
+    h->ny = dims[1];
+    h->nz = dims[2];
+    h->N = dims[0] * dims[1] * dims[2];
+    h->beta0 = beta0;
+    h->hc = host_constants(h->d);
+    KParams& p = h->kp;
+    p.nx = static_cast<int>(h->nx);
+    p.ny = static_cast<int>(h->ny);
+    p.nz = static_cast<int>(h->nz);
+    p.ncell = static_cast<int>(h->N);
+    p.Q = h->Q;
+    p.xi = h->hc.xi1 / std::sqrt(beta0);
+    p.beta0 = beta0;
+    p.half_xi2 = 0.5 * p.xi * p.xi;
+    p.a1_0 = h->hc.a1_0;
+    p.a1_b = h->hc.a1_b;
+    p.a2_0 = h->hc.a2_0;
+    p.a2_b = h->hc.a2_b;
+    p.a3 = h->hc.a3;
+    p.a4 = h->hc.a4;
+    p.a5 = h->hc.a5;
+    p.a3f = static_cast<float>(p.a3);
+    p.a4f = static_cast<float>(p.a4);
+    for (int i = 0; i < h->Q; ++i) {
+        int nz_ = 0;
+        for (int c = 0; c < 3; ++c) nz_ += (h->Q == 9 ? Lat<9>::c(i, c) : Lat<19>::c(i, c)) != 0;
+        p.w[i] = h->hc.wcls[nz_];
+    }
+    set_tau(h, tau);
+    for (int k = 0; k < 4; ++k)
+        for (int i = 0; i < 19; ++i) p.ref[k][i] = 0.0f;
+    for (int i = 0; i < 19; ++i) p.wS[i] = p.inv_wS[i] = 1.0f;
+    gauss_legendre(kGL, h->fp.gl_x, h->fp.gl_w);
+    *out = h;
+    return ok();
+}
+
+void mlbm_destroy(mlbm_handle h) {
+    if (!h) return;
+    if (h->d_partials) (void)hipFree(h->d_partials);
+    if (h->d_result) (void)hipFree(h->d_result);
+    delete h;
+}
+
+int mlbm_get_info(mlbm_handle h, mlbm_info* info) {
+    if (int e = check_handle(h)) return e;
+    if (!info) return fail(MLBM_EINVAL, "null info");
+    std::memset(info, 0, sizeof *info);
+    info->lattice = h->Q;
+    info->d = h->d;
+    info->storage = h->storage;
+    info->eq_mode = h->eq_mode;
+    info->nx = h->nx;
+    info->ny = h->ny;
+    info->nz = h->nz;
+    info->ncell = h->N;
+    info->tau = h->tau;
+    info->omega = h->kp.om;
+    info->beta0 = h->beta0;
+    info->xi = h->kp.xi;
+    info->a = h->hc.a;
+    for (int i = 0; i < h->Q; ++i) {
+        info->w[i] = h->kp.w[i];
+        for (int c = 0; c < 3; ++c) info->c[i][c] = h->Q == 9 ? Lat<9>::c(i, c) : Lat<19>::c(i, c);
+    }
+    info->a1_0 = h->kp.a1_0;
+    info->a1_b = h->kp.a1_b;
+    info->a2_0 = h->kp.a2_0;
+    info->a2_b = h->kp.a2_b;
+    info->a3 = h->kp.a3;
+    info->a4 = h->kp.a4;
+    info->a5 = h->kp.a5;
+    info->f16_scale = h->f16_scale;
+    for (int k = 0; k < 4; ++k)
+        for (int i = 0; i < h->Q; ++i) info->f16_ref[k][i] = h->f16_ref[k][i];
+    return ok();
+}
+
+int mlbm_field_bytes(mlbm_handle h, size_t* bytes) {
+    if (int e = check_handle(h)) return e;
+    if (!bytes) return fail(MLBM_EINVAL, "null bytes");
+    *bytes = static_cast<size_t>(4) * h->Q * static_cast<size_t>(h->N) * elem_size(h->storage);
+    return ok();
+}
+
+int mlbm_set_tau(mlbm_handle h, double tau) {
+    if (int e = check_handle(h)) return e;
+    if (!(std::isfinite(tau) && tau > 0.5)) return fail(MLBM_EDOMAIN, "tau must be finite and > 1/2 (got %g)", tau);
+    set_tau(h, tau);
+    return ok();
+}
+
+int mlbm_set_eq_mode(mlbm_handle h, int mode) {
+    if (int e = check_handle(h)) return e;
+    if (mode != MLBM_EQ_DIRECT && mode != MLBM_EQ_EIGEN) return fail(MLBM_EINVAL, "bad equilibrium mode");
+    if (mode == MLBM_EQ_EIGEN && h->storage != MLBM_STORE_F64)
+        return fail(MLBM_EINVAL, "the eigen-channel mode needs double storage");
+    h->eq_mode = mode;
+    return ok();
+}
+
+int mlbm_set_f16_reference(mlbm_handle h, const double* ref, double scale) {
+    if (int e = check_handle(h)) return e;
+    if (h->storage != MLBM_STORE_F16DEV) return fail(MLBM_EINVAL, "handle does not use F16DEV storage");
+    if (!ref) return fail(MLBM_EINVAL, "null reference");
+    if (!(std::isfinite(scale) && scale > 0.0)) return fail(MLBM_EINVAL, "scale must be finite and > 0");
+    for (int j = 0; j < 4 * h->Q; ++j)
+        if (!std::isfinite(ref[j])) return fail(MLBM_EINVAL, "non-finite reference value");
+    set_f16(h, ref, scale);
+    return ok();
+}
+
+int mlbm_init_equilibrium(mlbm_handle h, void* W, const double* rho4, const double* u, const double* T,
+                          void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!W || !rho4 || !u || !T) return fail(MLBM_EINVAL, "null argument");
+    if (int e = red_scratch(h)) return e;
+    hipStream_t s = as_stream(stream);
+    double r[kRedSlots];
+    if (h->storage == MLBM_STORE_F16DEV) {
+        // global means of the initial state (Eqs. GlobalDensity, GlobalVelocity, GlobalTotalEnergy)
+        HIP_TRY(launch_init(h->Q, h->storage, 0, W, rho4, u, T, h->kp, h->fp, h->d_partials, s));
+        HIP_TRY(launch_finalize(h->d_partials, kRedBlocks, kRedSlots, 0u, h->d_result, nullptr, 1.0, s));
+        if (int e = read_result(h, r, s)) return e;
+        if (int e = check_init_flags(r)) return e;
+        const double invN = 1.0 / static_cast<double>(h->N);
+        double rbar[4], ubar[3], uu = 0.0;
+        for (int k = 0; k < 4; ++k) rbar[k] = r[k] * invN;
+        for (int c = 0; c < 3; ++c) {
+            ubar[c] = r[4 + c] * invN / rbar[0];
+            uu += ubar[c] * ubar[c];
+        }
+        const double epsbar = r[7] * invN / rbar[0] - 0.5 * uu;
+        double ref[4 * 19];
+        for (int k = 0; k < 4; ++k)
+            for (int i = 0; i < h->Q; ++i) ref[k * h->Q + i] = h->kp.w[i] * rbar[k] * host_P(h, i, ubar, epsbar);
+        set_f16(h, ref, 1.0);
+        // largest scaled deviation max |a - R| / w_i fixes the power-of-two scale
+        HIP_TRY(launch_init(h->Q, h->storage, 1, W, rho4, u, T, h->kp, h->fp, h->d_partials, s));
+        HIP_TRY(launch_finalize(h->d_partials, kRedBlocks, kRedSlots, 1u, h->d_result, nullptr, 1.0, s));
+        if (int e = read_result(h, r, s)) return e;
+        if (int e = check_init_flags(r)) return e;
+        double scale = 1.0;
+        if (r[0] > 0.0) {
+            int ex = 0;
+            const double m = std::frexp(r[0], &ex);   // r0 = m 2^ex, m in [0.5, 1)
+            scale = std::ldexp(1.0, m == 0.5 ? ex - 1 : ex);
+        }
+        set_f16(h, ref, scale);
+    }
+    HIP_TRY(launch_init(h->Q, h->storage, 2, W, rho4, u, T, h->kp, h->fp, h->d_partials, s));
+    HIP_TRY(launch_finalize(h->d_partials, kRedBlocks, kRedSlots, 0u, h->d_result, nullptr, 1.0, s));
+    if (int e = read_result(h, r, s)) return e;
+    if (int e = check_init_flags(r)) return e;
+    return ok();
+}
+
+int mlbm_step(mlbm_handle h, void* W, void* scratch, int nsteps, void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!W || !scratch) return fail(MLBM_EINVAL, "null field");
+    if (W == scratch) return fail(MLBM_EINVAL, "W and scratch must be distinct");
+    if (nsteps < 0) return fail(MLBM_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return ok();
+    hipStream_t s = as_stream(stream);
+    const bool eig = h->eq_mode == MLBM_EQ_EIGEN;
+    auto run = [&](StepKind kind, const void* a, void* b) -> hipError_t {
+        if (eig && kind != StepKind::StreamOnly) return launch_step_eigen(kind, h->Q, a, b, h->kp, h->fp, nullptr, s);
+        return launch_step(kind, h->Q, h->storage, a, b, h->kp, s);
+    };
+    // After the collide-only pass and nsteps - 1 fused passes the
+    // post-collision state sits in `scratch`; the stream-only pass then
+    // returns the pre-collision state to W.
+    void* cur = (nsteps % 2 == 0) ? W : scratch;
+    void* other = (cur == W) ? scratch : W;
+    HIP_TRY(run(StepKind::CollideOnly, W, cur));
+    for (int j = 1; j < nsteps; ++j) {
+        HIP_TRY(run(StepKind::Fused, cur, other));
+        void* t = cur;
+        cur = other;
+        other = t;
+    }
+    HIP_TRY(run(StepKind::StreamOnly, cur, W));
+    return ok();
+}
+
+int mlbm_collide(mlbm_handle h, const void* src, void* dst, void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!src || !dst) return fail(MLBM_EINVAL, "null field");
+    hipStream_t s = as_stream(stream);
+    if (h->eq_mode == MLBM_EQ_EIGEN) HIP_TRY(launch_step_eigen(StepKind::CollideOnly, h->Q, src, dst, h->kp, h->fp, nullptr, s));
+    else HIP_TRY(launch_step(StepKind::CollideOnly, h->Q, h->storage, src, dst, h->kp, s));
+    return ok();
+}
+
+int mlbm_stream(mlbm_handle h, const void* src, void* dst, void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!src || !dst) return fail(MLBM_EINVAL, "null field");
+    if (src == dst) return fail(MLBM_EINVAL, "streaming needs distinct src and dst");
+    HIP_TRY(launch_step(StepKind::StreamOnly, h->Q, h->storage, src, dst, h->kp, as_stream(stream)));
+    return ok();
+}
+
+int mlbm_moments(mlbm_handle h, const void* W, double* rho4, double* u, double* eps, double* global8,
+                 int64_t* n_neg_eig, void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!W) return fail(MLBM_EINVAL, "null field");
+    if (int e = red_scratch(h)) return e;
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(launch_moments(h->Q, h->storage, W, rho4, u, eps, h->kp, h->d_partials, s));
+    if (!global8 && !n_neg_eig) return ok();
+    HIP_TRY(launch_finalize(h->d_partials, kRedBlocks, kRedSlots, 0u, h->d_result, nullptr, 1.0, s));
+    double r[kRedSlots];
+    if (int e = read_result(h, r, s)) return e;
+    if (global8) {
+        const double invN = 1.0 / static_cast<double>(h->N);
+        for (int k = 0; k < 8; ++k) global8[k] = r[k] * invN;
+    }
+    if (n_neg_eig) *n_neg_eig = static_cast<int64_t>(r[8]);
+    if (r[9] > 0) return fail(MLBM_ENONFINITE, "%.0f non-finite values in the field", r[9]);
+    return ok();
+}
+
+int mlbm_spin_loss(mlbm_handle h, const void* W, const double* r_target, double* loss, void* lam, void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!W || !r_target) return fail(MLBM_EINVAL, "null argument");
+    if (h->storage == MLBM_STORE_F16DEV) return fail(MLBM_EINVAL, "the spin loss needs F64 or F32 storage");
+    if (lam && lam == W) return fail(MLBM_EINVAL, "lam must not alias W");
+    if (int e = red_scratch(h)) return e;
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(launch_spin_loss(h->Q, h->storage, W, r_target, lam, h->kp, h->d_partials, s));
+    if (loss) {
+        HIP_TRY(launch_finalize(h->d_partials, kRedBlocks, kRedSlots, 0u, h->d_result, nullptr,
+                                1.0 / static_cast<double>(h->N), s));
+        HIP_TRY(hipMemcpyAsync(loss, h->d_result, sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    return ok();
+}
+
+int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next, void* lam_n, double* dL_domega,
+                      void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!W_n || !lam_next || !lam_n) return fail(MLBM_EINVAL, "null field");
+    if (h->storage == MLBM_STORE_F16DEV) return fail(MLBM_EINVAL, "the adjoint needs F64 or F32 storage");
+    if (h->eq_mode != MLBM_EQ_DIRECT) return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode");
+    if (lam_n == W_n || lam_n == lam_next) return fail(MLBM_EINVAL, "lam_n must not alias the inputs");
+    const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));
+    if (int e = ensure_scratch(h, std::max<size_t>(static_cast<size_t>(nb), static_cast<size_t>(kRedBlocks) * kRedSlots)))
+        return e;
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(launch_adjoint(h->Q, h->storage, W_n, lam_next, lam_n, h->kp, h->d_partials, s));
+    if (dL_domega) HIP_TRY(launch_finalize(h->d_partials, nb, 1, 0u, nullptr, dL_domega, 1.0, s));
+    return ok();
+}
+
+}  // extern "C"

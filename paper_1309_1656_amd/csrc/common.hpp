@@ -1,0 +1,116 @@
+// Shared device-side definitions: lattice tables, storage codecs, kernel
+// parameter block.
+//
+// Lattices (Sec. 3, Fig. 1; Sec. 3.1): velocities e_i = xi c_i with
+// c_i in {-1,0,1}^d, D3Q19 without the eight corners.  The enumeration order
+// is the one documented in include/mlbm.h: rest, axis pairs, diagonal pairs,
+// each velocity followed by its opposite.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mlbm {
+
+enum StoreMode { kF64 = 0, kF32 = 1, kF16Dev = 2 };
+
+template <int Q> struct Lat;
+
+template <> struct Lat<9> {
+    static constexpr int D = 2;
+    __host__ __device__ static constexpr int c(int i, int a) {
+        constexpr int t[9][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+                                 {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+        return t[i][a];
+    }
+};
+
+template <> struct Lat<19> {
+    static constexpr int D = 3;
+    __host__ __device__ static constexpr int c(int i, int a) {
+        constexpr int t[19][3] = {{0, 0, 0},   {1, 0, 0},  {-1, 0, 0},  {0, 1, 0},  {0, -1, 0},
+                                  {0, 0, 1},   {0, 0, -1}, {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},
+                                  {-1, 1, 0},  {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                                  {0, 1, 1},   {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+        return t[i][a];
+    }
+};
+
+template <int Q>
+__host__ __device__ constexpr int csq(int i) {
+    return Lat<Q>::c(i, 0) * Lat<Q>::c(i, 0) + Lat<Q>::c(i, 1) * Lat<Q>::c(i, 1) +
+           Lat<Q>::c(i, 2) * Lat<Q>::c(i, 2);
+}
+
+// Per-launch constants, passed by value as a kernel argument.  The host fills
+// both the double and the float copies; a kernel reads the copy of its
+// compute type.
+struct KParams {
+    int nx, ny, nz;
+    int ncell;
+    int Q;
+    // collision
+    double om, one_m_om;       // omega = Delta t / tau, 1 - omega
+    double xi, beta0;          // lattice constant, reference inverse temperature
+    double half_xi2;           // xi^2 / 2
+    double a1_0, a1_b, a2_0, a2_b, a3, a4, a5;   // Appendix coefficients
+    double w[19];              // cubature weights
+    double omw[19];            // omega * w_i
+    float omwf[19];
+    float one_m_omf, a3f, a4f;
+    // F16 scaled-deviation codec: a = ref[k][i] + wS[i] * h
+    float ref[4][19];
+    float wS[19];
+    float inv_wS[19];
+};
+
+template <int MODE> struct Store;
+template <> struct Store<kF64> { using T = double; using C = double; };
+template <> struct Store<kF32> { using T = float; using C = float; };
+template <> struct Store<kF16Dev> { using T = _Float16; using C = float; };
+
+template <int MODE>
+__device__ __forceinline__ typename Store<MODE>::C decode(typename Store<MODE>::T v, int k, int i,
+                                                          const KParams& p) {
+    if constexpr (MODE == kF16Dev) {
+        return p.ref[k][i] + p.wS[i] * static_cast<float>(v);
+    } else {
+        (void)k; (void)i; (void)p;
+        return v;
+    }
+}
+
+// Round to the storage type: round-to-nearest-even in every mode.
+template <int MODE>
+__device__ __forceinline__ typename Store<MODE>::T encode(typename Store<MODE>::C v, int k, int i,
+                                                          const KParams& p) {
+    if constexpr (MODE == kF16Dev) {
+        return static_cast<_Float16>((v - p.ref[k][i]) * p.inv_wS[i]);
+    } else {
+        (void)k; (void)i; (void)p;
+        return v;
+    }
+}
+
+// Compute-type views of the per-velocity constants.
+template <typename C> __device__ __forceinline__ C omw_of(const KParams& p, int i);
+template <> __device__ __forceinline__ double omw_of<double>(const KParams& p, int i) { return p.omw[i]; }
+template <> __device__ __forceinline__ float omw_of<float>(const KParams& p, int i) { return p.omwf[i]; }
+
+template <typename C> __device__ __forceinline__ C cst(double d, float f);
+template <> __device__ __forceinline__ double cst<double>(double d, float) { return d; }
+template <> __device__ __forceinline__ float cst<float>(double, float f) { return f; }
+
+// Periodic source coordinates of a pull: index [c + 1] holds (x - c) mod n.
+__device__ __forceinline__ void pull_coords(int x, int n, int stride, int out[3]) {
+    out[0] = ((x + 1 == n) ? 0 : x + 1) * stride;   // c = -1
+    out[1] = x * stride;                            // c =  0
+    out[2] = ((x == 0) ? n - 1 : x - 1) * stride;   // c = +1
+}
+
+// Number of double slots per block in the reduction scratch.
+constexpr int kRedSlots = 10;
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+
+}  // namespace mlbm

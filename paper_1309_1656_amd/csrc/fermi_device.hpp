@@ -1,0 +1,150 @@
+// Complete Fermi-Dirac integrals F_k(x) in double precision on the device,
+// and the inversion of the channel density n = (2 pi / beta)^(d/2)
+// F_{d/2-1}(nu) (Sec. 2.2, Eqs. nFDstdOmega and energyFDstdOmega).
+//
+// F_k(x) = Gamma(k+1)^-1 int_0^inf y^k / (e^(y-x) + 1) dy = -Li_{k+1}(-e^x),
+// dF_k/dx = F_{k-1}, F_{-1} = logistic, F_0 = log(1 + e^x) (Sec. 2.2).
+//
+// Methods (chosen here; the paper defers to the literature):
+//  * x <= -1: the polylogarithm series sum_j (-1)^(j+1) e^(j x) / j^(k+1),
+//    truncated when a term falls below 1e-18 of the sum (at most 60 terms).
+//  * half-integer k = m - 1/2, x > -1: with y = t^2 the integrand
+//    2 t^(2m) / (e^(t^2 - x) + 1) is even and analytic in the strip
+//    |Im t| < Im sqrt(x + i pi), so the trapezoidal rule on the half line
+//    converges geometrically; the step is 0.12 times that strip half-width
+//    (error ~ exp(-2 pi / 0.12)).  Supported for x <= 4000.
+//  * F_1 (d = 2 energy), x > -1: for x >= 1 the exact reflection
+//    F_1(x) = pi^2/6 + x^2/2 - F_1(-x); for -1 < x < 1,
+//    F_1(x) = F_1(-1) + int_{-1}^{x} F_0(s) ds by 20-point Gauss-Legendre
+//    (F_0 is analytic in a strip of half-width pi around the real axis).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace mlbm {
+namespace fd {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtPi = 1.77245385090551602730;
+
+__device__ __forceinline__ double logistic(double z) {
+    if (z >= 0.0) return 1.0 / (1.0 + exp(-z));
+    const double e = exp(z);
+    return e / (1.0 + e);
+}
+
+// j^(-s) for s = TWO_S / 2.
+template <int TWO_S>
+__device__ __forceinline__ double jpow_inv(int j) {
+    const double dj = static_cast<double>(j);
+    double p = 1.0;
+#pragma unroll
+    for (int r = 0; r < TWO_S / 2; ++r) p *= dj;
+    if (TWO_S & 1) p *= sqrt(dj);
+    return 1.0 / p;
+}
+
+// sum_{j>=1} (-1)^(j+1) e^(j x) / j^s, s = TWO_S / 2, for x <= -1.
+template <int TWO_S>
+__device__ double series(double x) {
+    const double t = exp(x);
+    double pj = t, sum = 0.0;
+    for (int j = 1; j <= 60; ++j) {
+        const double term = pj * jpow_inv<TWO_S>(j);
+        sum += (j & 1) ? term : -term;
+        if (term <= 1e-18 * sum) break;
+        pj *= t;
+    }
+    return sum;
+}
+
+// F_{M - 1/2}(x) by the trapezoidal rule described above, x > -1.
+// Arguments above kXMax (or NaN) return NaN: the step count grows like x,
+// and such degenerate states are outside the supported range.
+constexpr double kXMax = 4000.0;
+
+template <int M>
+__device__ double half_quad(double x) {
+    if (!(x <= kXMax)) return __builtin_nan("");
+    const double a = sqrt(0.5 * (sqrt(x * x + kPi * kPi) - x));
+    const double h = 0.12 * a;
+    const double tmax = sqrt(fmax(x, 0.0) + 50.0);
+    const int n = static_cast<int>(ceil(tmax / h));
+    double s = (M == 0) ? 0.5 * logistic(x) : 0.0;
+    for (int j = 1; j <= n; ++j) {
+        const double t = j * h;
+        const double t2 = t * t;
+        double pw = 1.0;
+#pragma unroll
+        for (int r = 0; r < M; ++r) pw *= t2;
+        s += pw * logistic(x - t2);
+    }
+    // Gamma(M + 1/2) = sqrt(pi) (2M)! / (4^M M!)
+    double g = kSqrtPi;
+#pragma unroll
+    for (int r = 1; r <= M; ++r) g *= (r - 0.5);
+    return 2.0 * h * s / g;
+}
+
+// F_{M - 1/2}(x), M = 0..3.
+template <int M>
+__device__ __forceinline__ double half(double x) {
+    return (x <= -1.0) ? series<2 * M + 1>(x) : half_quad<M>(x);
+}
+
+__device__ __forceinline__ double F0(double x) {
+    return (x <= 0.0) ? log1p(exp(x)) : x + log1p(exp(-x));
+}
+
+__device__ double F1(double x, const FdParams& fp) {
+    if (x <= -1.0) return series<4>(x);
+    if (x >= 1.0) return kPi * kPi / 6.0 + 0.5 * x * x - series<4>(-x);
+    // F_1(-1) + int_{-1}^{x} F_0(s) ds
+    const double half_len = 0.5 * (x + 1.0), mid = 0.5 * (x - 1.0);
+    double s = 0.0;
+    for (int j = 0; j < kGL; ++j) s += fp.gl_w[j] * F0(mid + half_len * fp.gl_x[j]);
+    return series<4>(-1.0) + half_len * s;
+}
+
+// nu with F_{1/2}(nu) = c (c > 0), Newton with F_{-1/2} as derivative.
+// F_{1/2} is increasing and convex, so after at most one overshoot the
+// iterates approach the root monotonically.  Returns false on failure.
+__device__ bool invert_half(double c, double& nu) {
+    nu = (c < 1.0) ? log(c) : pow(c * 1.32934038817913702047, 2.0 / 3.0);  // Gamma(5/2) c
+    for (int it = 0; it < 60; ++it) {
+        const double f = half<1>(nu) - c;
+        const double d = f / half<0>(nu);
+        nu -= d;
+        if (!isfinite(nu)) return false;
+        if (fabs(d) <= 2e-15 * fmax(1.0, fabs(nu))) return true;
+    }
+    return false;
+}
+
+// nu = beta mu of a channel with density n at inverse temperature beta.
+template <int D>
+__device__ __forceinline__ bool channel_nu(double n, double beta, double& nu) {
+    if constexpr (D == 2) {
+        nu = log(expm1(n * beta / (2.0 * kPi)));       // F_0 has a closed-form inverse
+        return isfinite(nu);
+    } else {
+        const double s = beta / (2.0 * kPi);
+        return invert_half(n * s * sqrt(s), nu);
+    }
+}
+
+// eps_FD of Eq. energyFDstdOmega.
+template <int D>
+__device__ __forceinline__ double internal_energy(double beta, double nu_up, double nu_dn,
+                                                  const FdParams& fp) {
+    if constexpr (D == 2) {
+        return (F1(nu_up, fp) + F1(nu_dn, fp)) / (beta * (F0(nu_up) + F0(nu_dn)));
+    } else {
+        return 1.5 * (half<2>(nu_up) + half<2>(nu_dn)) / (beta * (half<1>(nu_up) + half<1>(nu_dn)));
+    }
+}
+
+}  // namespace fd
+}  // namespace mlbm

@@ -1,0 +1,61 @@
+// Host-side declarations shared by the C-ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace mlbm {
+
+enum class StepKind { Fused, CollideOnly, StreamOnly };
+
+// Gauss-Legendre rule on [-1, 1] used by the device Fermi-Dirac integrals.
+constexpr int kGL = 20;
+struct FdParams {
+    double gl_x[kGL];
+    double gl_w[kGL];
+};
+
+hipError_t launch_step(StepKind kind, int Q, int mode, const void* src, void* dst, const KParams& p,
+                       hipStream_t s);
+
+// Eigen-channel variant of the fused / collide-only pass (double storage only).
+hipError_t launch_step_eigen(StepKind kind, int Q, const void* src, void* dst, const KParams& p,
+                             const FdParams& fp, double* partials, hipStream_t s);
+
+// Per-cell moments and block partial sums.  partials: kRedBlocks x kRedSlots.
+//   slots 0..3 sum of rho_k, 4..6 sum of tr(rho) u, 7 sum of total energy,
+//   8 number of populations with a negative eigenvalue, 9 number of
+//   non-finite values.
+hipError_t launch_moments(int Q, int mode, const void* W, double* rho4, double* u, double* eps,
+                          const KParams& p, double* partials, hipStream_t s);
+
+// Spin loss: slot 0 partial sum of |r - r_target|^2; optional adjoint seed.
+hipError_t launch_spin_loss(int Q, int mode, const void* W, const double* r_target, void* lam,
+                            const KParams& p, double* partials, hipStream_t s);
+
+// Adjoint of one step: one partial of dL/domega per block
+// (adjoint_blocks(nx, ny, nz) values, stride 1).
+hipError_t launch_adjoint(int Q, int mode, const void* Wn, const void* lam_next, void* lam_n,
+                          const KParams& p, double* partials, hipStream_t s);
+
+// Initial Fermi-Dirac state.  phase 0: only reduce global sums (slots 0..3
+// rho_k, 4..6 tr(rho) u, 7 total energy); phase 1: reduce max |a - R| / w_i
+// into slot 0 (max); phase 2: write W.  Slots 8, 9 count domain errors and
+// failed inversions in every phase.
+hipError_t launch_init(int Q, int mode, int phase, void* W, const double* rho4, const double* u,
+                       const double* T, const KParams& p, const FdParams& fp, double* partials,
+                       hipStream_t s);
+
+// Reduce nblocks rows of `stride` partials (stride <= kRedSlots) to one
+// value per slot in a fixed order.  Bit s of max_mask selects a max instead of
+// a sum for slot s.  Slot 0 is multiplied by scale0.  When accumulate_into is
+// non-null, only slot 0 is produced and added to *accumulate_into; otherwise
+// kRedSlots values go to out (slots >= stride are 0).
+hipError_t launch_finalize(const double* partials, int nblocks, int stride, unsigned max_mask, double* out,
+                           double* accumulate_into, double scale0, hipStream_t s);
+
+// Number of blocks (= partials) of launch_adjoint for a grid.
+int adjoint_blocks(int nx, int ny, int nz);
+
+}  // namespace mlbm

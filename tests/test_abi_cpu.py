@@ -1,0 +1,106 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/mlbm.h declares, validates arguments on the host, and computes the
+same constants as the oracle (mlbm_create touches no device memory)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import lattice as olat
+from oracle import qlbm
+from paper_1309_1656_amd import mlbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mlbm.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(mlbm.LIB_PATH), reason="libmlbm.so not built")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlbm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = ctypes.CDLL(mlbm.LIB_PATH)
+    declared = _declared()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(mlbm.EXPORTS)
+
+
+@pytest.mark.parametrize("lattice,d,dims", [(9, 2, (16, 12, 1)), (19, 3, (8, 7, 6))])
+@pytest.mark.parametrize("beta0", [0.8, 1.0, 1.2])
+def test_constants_match_oracle(lattice, d, dims, beta0):
+    h = mlbm.mlbm_create(lattice, dims, 0.8, beta0, mlbm.MLBM_STORE_F64)
+    info = h.info
+    lat = qlbm.Lattice(d, beta0)
+    assert info["d"] == d and info["ncell"] == int(np.prod(dims))
+    assert abs(info["xi"] / lat.xi - 1) < 1e-15
+    assert np.max(np.abs(info["w"] / lat.w - 1)) < 1e-15
+    assert np.array_equal(info["c"][:, :d], olat.velocities(d))
+    for key in ("a1_0", "a1_b", "a2_0", "a2_b", "a3", "a4", "a5"):
+        assert abs(info[key] / lat.coef[key] - 1) < 1e-15, key
+    assert abs(info["omega"] - 1 / 0.8) < 1e-16
+    h.destroy()
+
+
+def test_field_bytes():
+    for storage, size in [(0, 8), (1, 4), (2, 2)]:
+        h = mlbm.mlbm_create(19, (5, 6, 7), 0.8, 1.0, storage)
+        assert mlbm.mlbm_field_bytes(h) == 4 * 19 * 5 * 6 * 7 * size
+
+
+@pytest.mark.parametrize("args,code", [
+    ((10, (8, 8, 1), 0.8, 1.0, 0), mlbm.MLBM_EINVAL),     # bad lattice
+    ((9, (8, 8, 2), 0.8, 1.0, 0), mlbm.MLBM_EINVAL),      # D2Q9 with nz != 1
+    ((9, (0, 8, 1), 0.8, 1.0, 0), mlbm.MLBM_EINVAL),      # empty grid
+    ((19, (8, 8, 8), 0.8, 1.0, 3), mlbm.MLBM_EINVAL),     # bad storage
+    ((19, (1 << 16, 1 << 10, 1 << 6), 0.8, 1.0, 0), mlbm.MLBM_EINVAL),   # 2^32 cells
+    ((19, (8, 70000, 8), 0.8, 1.0, 0), mlbm.MLBM_EINVAL),  # ny too large
+    ((9, (8, 8, 1), 0.5, 1.0, 0), mlbm.MLBM_EDOMAIN),     # tau = 1/2
+    ((9, (8, 8, 1), float("nan"), 1.0, 0), mlbm.MLBM_EDOMAIN),
+    ((9, (8, 8, 1), 0.8, 0.0, 0), mlbm.MLBM_EDOMAIN),     # beta0 = 0
+    ((9, (8, 8, 1), 0.8, float("inf"), 0), mlbm.MLBM_EDOMAIN),
+])
+def test_create_rejects(args, code):
+    with pytest.raises(mlbm.MlbmError) as e:
+        mlbm.mlbm_create(*args)
+    assert e.value.code == code
+    assert mlbm.mlbm_last_error()
+
+
+def test_host_side_validation():
+    h = mlbm.mlbm_create(9, (8, 8, 1), 0.8, 1.0, mlbm.MLBM_STORE_F32)
+    lib = mlbm.load_library()
+    with pytest.raises(mlbm.MlbmError) as e:
+        mlbm.mlbm_set_tau(h, 0.3)
+    assert e.value.code == mlbm.MLBM_EDOMAIN
+    with pytest.raises(mlbm.MlbmError) as e:
+        mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_EIGEN)      # eigen mode needs F64
+    assert e.value.code == mlbm.MLBM_EINVAL
+    with pytest.raises(mlbm.MlbmError):
+        mlbm.mlbm_set_eq_mode(h, 7)
+    # null / aliasing pointers are rejected before any device work
+    assert lib.mlbm_step(h.ptr, None, None, 3, None) == mlbm.MLBM_EINVAL
+    buf = ctypes.c_void_p(4096)
+    assert lib.mlbm_step(h.ptr, buf, buf, 3, None) == mlbm.MLBM_EINVAL
+    assert lib.mlbm_step(h.ptr, buf, ctypes.c_void_p(8192), -1, None) == mlbm.MLBM_EINVAL
+    assert lib.mlbm_step(h.ptr, buf, ctypes.c_void_p(8192), 0, None) == mlbm.MLBM_OK   # no-op
+    assert lib.mlbm_stream(h.ptr, buf, buf, None) == mlbm.MLBM_EINVAL
+    assert lib.mlbm_adjoint_step(h.ptr, buf, buf, buf, None, None) == mlbm.MLBM_EINVAL
+    assert lib.mlbm_init_equilibrium(h.ptr, buf, None, buf, buf, None) == mlbm.MLBM_EINVAL
+    assert lib.mlbm_set_f16_reference(h.ptr, None, 1.0) == mlbm.MLBM_EINVAL
+    assert lib.mlbm_get_info(None, None) == mlbm.MLBM_EINVAL
+    h16 = mlbm.mlbm_create(9, (8, 8, 1), 0.8, 1.0, mlbm.MLBM_STORE_F16DEV)
+    assert lib.mlbm_spin_loss(h16.ptr, buf, buf, None, None, None) == mlbm.MLBM_EINVAL
+    ref = np.arange(36, dtype=np.float64)
+    mlbm.mlbm_set_f16_reference(h16, ref, 0.25)
+    assert h16.info["f16_scale"] == 0.25
+    assert np.array_equal(h16.info["f16_ref"].ravel(), ref)
+    with pytest.raises(mlbm.MlbmError):
+        mlbm.mlbm_set_f16_reference(h16, ref, -1.0)

@@ -1,0 +1,119 @@
+"""GPU adjoint against the oracle's hand-derived adjoint and against finite
+differences of the GPU forward step, through the C ABI and the autograd
+wrapper."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import fields, gpu_init, make_handle, normwise_rel_err, oracle_init, oracle_pauli, to_pauli_np
+from oracle import adjoint, pauli, qlbm
+from paper_1309_1656_amd import mlbm, synthetic
+from paper_1309_1656_amd.rollout import MLBMRollout
+
+pytestmark = pytest.mark.gpu
+
+
+def _perturbed(lat, W, seed=5, amp=0.02):
+    rng = np.random.default_rng(seed)
+    a = rng.normal(0, amp, size=(4,) + W.shape[:-2]) * lat.w.reshape((1, -1) + (1,) * lat.d)
+    return W + pauli.matrix_from_pauli(a)
+
+
+@pytest.mark.parametrize("shape", [(37, 70), (13, 9, 11)])
+def test_adjoint_step_matches_oracle(shape):
+    print(f"adjoint step {shape}", flush=True)
+    f = fields(shape, 12)
+    lat, Wo = oracle_init(shape, f)
+    Wo = _perturbed(lat, Wo)
+    rng = np.random.default_rng(4)
+    lam1 = rng.standard_normal((4, lat.Q) + tuple(shape))
+    h = make_handle(shape, tau=0.7)
+    lam0 = h.empty_field()
+    dom = torch.full((1,), 0.25, dtype=torch.float64, device="cuda")
+    mlbm.mlbm_adjoint_step(h, torch.from_numpy(oracle_pauli(Wo)).cuda(), torch.from_numpy(lam1).cuda(), lam0, dom)
+    L0, dom_o = adjoint.step_vjp(lat, Wo, pauli.matrix_from_pauli(2.0 * lam1), 0.7)
+    ref = pauli.pauli_from_matrix(L0) / 2.0
+    assert normwise_rel_err(to_pauli_np(lam0), ref) < 1e-12
+    assert abs((dom.item() - 0.25) - dom_o) <= 1e-11 * abs(dom_o)
+
+
+def _loss_and_grad(h, W0, tau, steps, K, rt):
+    W0 = W0.clone().requires_grad_(True)
+    tau_t = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+    loss = MLBMRollout.apply(W0, tau_t, h, steps, K, rt)
+    loss.backward()
+    return loss.item(), W0.grad, tau_t.grad.item()
+
+
+@pytest.mark.parametrize("K", [3, 10, 20])
+def test_rollout_gradient_matches_oracle(K):
+    shape, tau, steps = (16, 16), 0.8, 10
+    f = fields(shape, synthetic.BASE_SEED + 5)
+    rt_np = synthetic.target_bloch_field(shape, synthetic.BASE_SEED + 105)
+    h = make_handle(shape, tau=tau)
+    W0 = gpu_init(h, f)
+    L, gW, gtau = _loss_and_grad(h, W0, tau, steps, K, torch.from_numpy(rt_np).cuda())
+    lat, Wo = oracle_init(shape, f)
+    Lo, Lam0, dtau_o = adjoint.rollout_grad(lat, Wo, tau, steps, rt_np)
+    assert abs(L / Lo - 1) < 1e-12
+    assert normwise_rel_err(to_pauli_np(gW), pauli.pauli_from_matrix(Lam0) / 2.0) < 1e-11
+    assert abs(gtau / dtau_o - 1) < 1e-11
+
+
+def test_rollout_gradient_matches_gpu_finite_differences():
+    shape, tau, steps = (16, 16), 0.8, 10
+    f = fields(shape, synthetic.BASE_SEED + 5)
+    rt = torch.from_numpy(synthetic.target_bloch_field(shape, synthetic.BASE_SEED + 105)).cuda()
+    h = make_handle(shape, tau=tau)
+    W0 = gpu_init(h, f)
+    L, gW, gtau = _loss_and_grad(h, W0, tau, steps, 4, rt)
+
+    def loss_at(W, t):
+        with torch.no_grad():
+            return MLBMRollout.apply(W, torch.tensor(t, dtype=torch.float64), h, steps, 4, rt).item()
+
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        dW = torch.from_numpy(rng.standard_normal(W0.shape) * 1e-3).cuda()
+        e = 1e-4
+        fd = (loss_at(W0 + e * dW, tau) - loss_at(W0 - e * dW, tau)) / (2 * e)
+        an = float((gW * dW).sum())
+        assert abs(an - fd) <= 1e-6 * max(abs(fd), 1e-8)
+    e = 1e-5
+    fd = (loss_at(W0, tau + e) - loss_at(W0, tau - e)) / (2 * e)
+    assert abs(gtau - fd) <= 1e-6 * abs(fd)
+
+
+def test_f32_rollout_against_f64_oracle():
+    """FP32 forward + adjoint (checkpoints every 20) vs the FP64 oracle: error reported."""
+    shape, tau, steps = (64, 64), 0.8, 200
+    f = fields(shape, synthetic.BASE_SEED + 5)
+    rt_np = synthetic.target_bloch_field(shape, synthetic.BASE_SEED + 105)
+    h = make_handle(shape, tau=tau, storage=mlbm.MLBM_STORE_F32)
+    W0 = gpu_init(h, f)
+    L, gW, gtau = _loss_and_grad(h, W0, tau, steps, 20, torch.from_numpy(rt_np).cuda())
+    lat, Wo = oracle_init(shape, f)
+    Lo, Lam0, dtau_o = adjoint.rollout_grad(lat, Wo, tau, steps, rt_np)
+    gerr = normwise_rel_err(to_pauli_np(gW), pauli.pauli_from_matrix(Lam0) / 2.0)
+    print(f"f32 rollout: loss rel err {abs(L / Lo - 1):.2e}, grad W0 {gerr:.2e}, grad tau {abs(gtau / dtau_o - 1):.2e}")
+    assert abs(L / Lo - 1) < 1e-5
+    assert gerr < 1e-4
+    assert abs(gtau / dtau_o - 1) < 1e-4
+
+
+def test_spin_loss_matches_oracle():
+    shape = (13, 9, 11)
+    f = fields(shape, 3)
+    rt_np = synthetic.target_bloch_field(shape, 77)
+    h = make_handle(shape)
+    W = gpu_init(h, f)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lam = h.empty_field()
+    mlbm.mlbm_spin_loss(h, W, torch.from_numpy(rt_np).cuda(), loss=loss, lam=lam)
+    lat, Wo = oracle_init(shape, f)
+    Lo, Lam = adjoint.spin_loss(lat, Wo, rt_np)
+    assert abs(loss.item() / Lo - 1) < 1e-13
+    ref = pauli.pauli_from_matrix(Lam) / 2.0
+    got = to_pauli_np(lam)
+    assert np.all(got[0] == 0)
+    assert np.max(np.abs(got[1:] - ref[1:])) <= 1e-13 * np.abs(ref[1:]).max()
