@@ -40,35 +40,60 @@ def _modes(d):
     return out
 
 
-def smooth_field(rng, shape):
-    """One normalised smooth periodic field on grid ``shape`` = (y, x) or (z, y, x)."""
+def _spectrum(rng, shape):
+    """Fourier coefficients {array index: complex} of one smooth field."""
     d = len(shape)
     ks = _modes(d)
     amp = rng.standard_normal(len(ks)) / np.array([float(sum(v * v for v in k)) for k in ks])
     phase = rng.uniform(0.0, 2.0 * np.pi, len(ks))
-    spec = np.zeros(shape, dtype=np.complex128)
     ncell = int(np.prod(shape))
+    coef = {}
     for k, A, ph in zip(ks, amp, phase):
         # k is (k_x, k_y[, k_z]); array axes are reversed (x fastest)
         idx = tuple(k[d - 1 - ax] % shape[ax] for ax in range(d))
-        spec[idx] += ncell * A * np.exp(1j * ph)
-    f = np.real(np.fft.ifftn(spec))
-    return f / np.abs(f).max()
+        coef[idx] = coef.get(idx, 0.0) + ncell * A * np.exp(1j * ph)
+    return coef
+
+
+def smooth_field(rng, shape, device=None):
+    """One normalised smooth periodic field on grid ``shape`` = (y, x) or (z, y, x).
+
+    With ``device`` (a torch device) the inverse FFT runs there and a torch
+    tensor is returned; the values equal the NumPy ones up to rounding.
+    """
+    coef = _spectrum(rng, shape)
+    if device is None:
+        spec = np.zeros(shape, dtype=np.complex128)
+        for idx, c in coef.items():
+            spec[idx] = c
+        f = np.real(np.fft.ifftn(spec))
+        return f / np.abs(f).max()
+    import torch
+    spec = torch.zeros(shape, dtype=torch.complex128, device=device)
+    for idx, c in coef.items():
+        spec[idx] = complex(c)
+    f = torch.fft.ifftn(spec).real.contiguous()
+    del spec
+    return f / f.abs().max()
 
 
 def _normalise_vec(v, amp):
-    norm = np.sqrt((v ** 2).sum(axis=0)).max()
+    norm = (v ** 2).sum(axis=0).max() ** 0.5
     return v * (amp / norm)
 
 
-def macroscopic_fields(shape, seed):
-    """dict(trrho [*shape], r [3, *shape], u_lat [d, *shape], T [*shape]) as float64."""
+def macroscopic_fields(shape, seed, device=None):
+    """dict(trrho [*shape], r [3, *shape], u_lat [d, *shape], T [*shape], s [3, *shape]).
+
+    float64 NumPy arrays, or torch tensors on ``device`` when given.
+    """
     d = len(shape)
     rng = np.random.default_rng(np.random.PCG64(seed))
-    f = [smooth_field(rng, shape) for _ in range(8)]
+    f = [smooth_field(rng, shape, device) for _ in range(8)]
+    stack = np.stack if device is None else __import__("torch").stack
     trrho = 1.0 + 0.1 * f[0]
-    s = _normalise_vec(np.stack(f[1:4]), 0.3)
-    u_lat = _normalise_vec(np.stack(f[4:4 + d]), 0.05)
+    s = _normalise_vec(stack(f[1:4]), 0.3)
+    u_lat = _normalise_vec(stack(f[4:4 + d]), 0.05)
     T = 1.0 + 0.05 * f[7]
     return {"trrho": trrho, "r": trrho[None] * s, "u_lat": u_lat, "T": T, "s": s}
 
