@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, AMD published peak
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_d3q19_128_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1309_1656_amd", "csrc", f) for f in ("step.hip", "common.hpp")]
 
 
 def log(msg):
@@ -42,6 +44,8 @@ def parse():
     ap.add_argument("--workload", default="d3q19_128")
     ap.add_argument("--skip-extras", action="store_true", help="only the FP64 headline measurement")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -154,6 +158,36 @@ def copy_bandwidth():
     return 2 * n * 8 / (ms * 1e-3) / 1e9
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per fused-kernel launch from the stored counter summary, if it matches the current kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return t["hbm_bytes_per_launch"]
+
+
+def copy_probe():
+    import torch
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+
 def cpu_baseline(seconds=12.0):
     """The FP64 oracle on a bounded sample: D3Q19 48^3 cells, steps until ~seconds."""
     from oracle import qlbm
@@ -220,7 +254,9 @@ def main():
                                f"smooth Fermi-Dirac initial state, FP64 storage",
                    "lattice": "D2Q9" if Q == 9 else "D3Q19", "grid": list(reversed(shape)), "tau": tau},
         "roofline": {"bound": "hbm", "achieved": r64["fused_kernel_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r64["fused_kernel_GBps"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": r64["fused_kernel_GBps"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if args.workload == "d3q19_128" else None,
+                     "algorithmic_bytes_per_launch": r64["bytes_per_cell"] * int(np.prod(shape)),
                      "kernel": "k_step<19, F64, pull, collide>", "kernel_ms": r64["fused_kernel_ms"],
                      "bytes_per_cell": r64["bytes_per_cell"]},
         "f64": r64,
@@ -230,6 +266,8 @@ def main():
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline()
         log(f"  {line['cpu_baseline']['value']:.3f} MLUPS")
+    if args.copy_probe:
+        copy_probe()
     print(json.dumps(line), flush=True)
 
 

@@ -22,12 +22,15 @@
  *   {1-12a, a, a/2} by number of nonzero components (Eqs. QuadSolution2D/3D at
  *   mu0 = 0, Eqs. QuadSolution2Dmu0 / QuadSolution3Dmu0).
  *
- * Field layout ("a field").  Structure of arrays, one contiguous plane of N
- * cells per (Pauli component k, velocity i):
- *     element (k, i, cell) at offset ((k * Q) + i) * N + cell,
- *     cell = x + nx * (y + ny * z),  N = nx * ny * nz,
- * i.e. a C-contiguous array [4][Q][nz][ny][nx] of the storage type.  Periodic
- * boundaries in every direction (Sec. 3).  Storage types:
+ * Field layout ("a field").  Row-blocked structure of arrays: cells are
+ * grouped in x-rows, row = y + ny * z, and each row holds 4 * Q contiguous
+ * segments of nx values, one per (Pauli component k, velocity i):
+ *     element (k, i, x, y, z) at ((row * 4 + k) * Q + i) * nx + x,
+ * i.e. a C-contiguous array [nz][ny][4][Q][nx] of the storage type (nz = 1
+ * in 2D).  Lanes along x access consecutive addresses, and one row's update
+ * writes one contiguous block.  Periodic boundaries in every direction
+ * (Sec. 3).  Per-cell arrays (rho4, u, T, eps, r_target) are plain planes
+ * [rows][N] with cell = x + nx * (y + ny * z).  Storage types:
  *   MLBM_STORE_F64     double; all arithmetic in double.
  *   MLBM_STORE_F32     float; collision arithmetic in float, moment sums in
  *                      double.

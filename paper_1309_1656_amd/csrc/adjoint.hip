@@ -39,24 +39,24 @@ k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<M
     const int z = blockIdx.z;
     double dom = 0.0;
     if (x < p.nx && y < p.ny) {
-        const int nxy = p.nx * p.ny;
-        const int node = x + p.nx * y + nxy * z;
-        const size_t N = static_cast<size_t>(p.ncell);
-        int sn[Q];
-        {
-            int xo[3], yo[3], zo[3];
-            push_coords(x, p.nx, 1, xo);
-            push_coords(y, p.ny, p.nx, yo);
-            if constexpr (D == 3) push_coords(z, p.nz, nxy, zo);
-            else zo[0] = zo[1] = zo[2] = 0;
+        const int nx = p.nx, ny = p.ny, nz = p.nz;
+        const size_t row = static_cast<size_t>(z) * ny + y;
+        // neighbour coordinates x + c along each axis, indexed by c + 1
+        int xp[3], yp[3], zp[3] = {z, z, z};
+        push_coords(x, nx, 1, xp);
+        push_coords(y, ny, 1, yp);
+        if constexpr (D == 3) push_coords(z, nz, 1, zp);
+        size_t srow[Q];
+        int sx[Q];
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-                sn[i] = xo[Lat<Q>::c(i, 0) + 1] + yo[Lat<Q>::c(i, 1) + 1] + zo[Lat<Q>::c(i, 2) + 1];
+        for (int i = 0; i < Q; ++i) {
+            srow[i] = static_cast<size_t>(zp[Lat<Q>::c(i, 2) + 1]) * ny + yp[Lat<Q>::c(i, 1) + 1];
+            sx[i] = xp[Lat<Q>::c(i, 0) + 1];
         }
         // trace channel of W_n: moments and the polynomial factor
         double a0[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) a0[i] = static_cast<double>(Wn[i * N + node]);
+        for (int i = 0; i < Q; ++i) a0[i] = static_cast<double>(Wn[fidx(Q, nx, row, 0, i, x)]);
         double Tr = 0.0, J[3] = {0.0, 0.0, 0.0}, K = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -89,7 +89,7 @@ k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<M
         double h0 = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            g0[i] = static_cast<double>(ln1[i * N + sn[i]]);
+            g0[i] = static_cast<double>(ln1[fidx(Q, nx, srow[i], 0, i, sx[i])]);
             h0 += g0[i] * wP[i];
             dom += g0[i] * (wP[i] * Tr - a0[i]);
             G[i] = p.w[i] * g0[i] * Tr;
@@ -101,20 +101,20 @@ k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<M
             double rk = 0.0;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                ak[i] = static_cast<double>(Wn[(k * Q + i) * N + node]);
+                ak[i] = static_cast<double>(Wn[fidx(Q, nx, row, k, i, x)]);
                 rk += ak[i];
             }
             double hk = 0.0;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                gk[i] = static_cast<double>(ln1[(k * Q + i) * N + sn[i]]);
+                gk[i] = static_cast<double>(ln1[fidx(Q, nx, srow[i], k, i, sx[i])]);
                 hk += gk[i] * wP[i];
                 dom += gk[i] * (wP[i] * rk - ak[i]);
                 G[i] += p.w[i] * gk[i] * rk;
             }
             const double mix = om * hk;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) ln[(k * Q + i) * N + node] = static_cast<T>(omm * gk[i] + mix);
+            for (int i = 0; i < Q; ++i) ln[fidx(Q, nx, row, k, i, x)] = static_cast<T>(omm * gk[i] + mix);
         }
         // G_u, G_eps and the trace-channel output
         double Gu[3] = {0.0, 0.0, 0.0}, Gsum = 0.0, Ge = 0.0;
@@ -140,7 +140,7 @@ k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<M
                 gdu += Gu[c] * dv;
                 dev2 += dv * dv;
             }
-            ln[j * N + node] = static_cast<T>(omm * g0[j] + mix0 + sc * (gdu + Ge * (0.5 * dev2 - eps)));
+            ln[fidx(Q, nx, row, 0, j, x)] = static_cast<T>(omm * g0[j] + mix0 + sc * (gdu + Ge * (0.5 * dev2 - eps)));
         }
     }
     // block partial of dL/domega (fixed tree: reproducible)

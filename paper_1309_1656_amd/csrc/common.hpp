@@ -101,6 +101,16 @@ template <typename C> __device__ __forceinline__ C cst(double d, float f);
 template <> __device__ __forceinline__ double cst<double>(double d, float) { return d; }
 template <> __device__ __forceinline__ float cst<float>(double, float f) { return f; }
 
+// Field layout: row-blocked structure of arrays.  Cells are grouped in
+// x-rows (row = y + ny * z); each row holds 4 * Q contiguous segments of nx
+// values, one per (Pauli component k, velocity i):
+//     element (k, i, x, row) at ((row * 4 + k) * Q + i) * nx + x.
+// Lanes along x read and write consecutive addresses of one segment, and a
+// workgroup's writes fill one contiguous block of its row.
+__host__ __device__ __forceinline__ size_t fidx(int Q, int nx, size_t row, int k, int i, int x) {
+    return ((row * 4 + static_cast<size_t>(k)) * Q + i) * static_cast<size_t>(nx) + x;
+}
+
 // Periodic source coordinates of a pull: index [c + 1] holds (x - c) mod n.
 __device__ __forceinline__ void pull_coords(int x, int n, int stride, int out[3]) {
     out[0] = ((x + 1 == n) ? 0 : x + 1) * stride;   // c = -1

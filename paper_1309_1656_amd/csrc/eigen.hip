@@ -95,22 +95,20 @@ k_step_eigen(const double* __restrict__ src, double* __restrict__ dst, const KPa
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
     if (x >= p.nx || y >= p.ny) return;
-    const int nxy = p.nx * p.ny;
-    const int node = x + p.nx * y + nxy * z;
-    const size_t N = static_cast<size_t>(p.ncell);
-    int sn[Q];
-    if constexpr (PULL) {
-        int xo[3], yo[3], zo[3];
-        pull_coords(x, p.nx, 1, xo);
-        pull_coords(y, p.ny, p.nx, yo);
-        if constexpr (D == 3) pull_coords(z, p.nz, nxy, zo);
-        else zo[0] = zo[1] = zo[2] = 0;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const size_t row = static_cast<size_t>(z) * ny + y;
+    size_t srow[Q];
+    int sx[Q];
+    {
+        int xo[3], yo[3], zo[3] = {z, z, z};
+        pull_coords(x, nx, 1, xo);
+        pull_coords(y, ny, 1, yo);
+        if constexpr (D == 3) pull_coords(z, nz, 1, zo);
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            sn[i] = xo[Lat<Q>::c(i, 0) + 1] + yo[Lat<Q>::c(i, 1) + 1] + zo[Lat<Q>::c(i, 2) + 1];
-    } else {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) sn[i] = node;
+        for (int i = 0; i < Q; ++i) {
+            srow[i] = PULL ? static_cast<size_t>(zo[Lat<Q>::c(i, 2) + 1]) * ny + yo[Lat<Q>::c(i, 1) + 1] : row;
+            sx[i] = PULL ? xo[Lat<Q>::c(i, 0) + 1] : x;
+        }
     }
     double a[4][Q];
     double rho[4] = {0.0, 0.0, 0.0, 0.0}, J[3] = {0.0, 0.0, 0.0}, K = 0.0;
@@ -118,7 +116,7 @@ k_step_eigen(const double* __restrict__ src, double* __restrict__ dst, const KPa
     for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            a[k][i] = src[(k * Q + i) * N + sn[i]];
+            a[k][i] = src[fidx(Q, nx, srow[i], k, i, sx[i])];
             rho[k] += a[k][i];
         }
 #pragma unroll
@@ -163,7 +161,7 @@ k_step_eigen(const double* __restrict__ src, double* __restrict__ dst, const KPa
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const double weq = p.w[i] * req[k] * P;
-            dst[(k * Q + i) * N + node] = a[k][i] + p.om * (weq - a[k][i]) + bad;
+            dst[fidx(Q, nx, row, k, i, x)] = a[k][i] + p.om * (weq - a[k][i]) + bad;
         }
     }
 }

@@ -75,7 +75,8 @@ k_init(typename Store<MODE>::T* __restrict__ W, const double* __restrict__ rho4,
                 if (PHASE == 1) {
                     acc[0] = fmax(acc[0], fabs(wv - static_cast<double>(p.ref[k][i])) / p.w[i]);
                 } else {
-                    W[(k * Q + i) * N + n] = encode<MODE>(static_cast<typename Store<MODE>::C>(wv), k, i, p);
+                    W[fidx(Q, p.nx, n / p.nx, k, i, static_cast<int>(n % p.nx))] =
+                        encode<MODE>(static_cast<typename Store<MODE>::C>(wv), k, i, p);
                 }
             }
         }

@@ -20,11 +20,14 @@ k_moments(const typename Store<MODE>::T* __restrict__ W, double* __restrict__ rh
 
     for (size_t n = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; n < N;
          n += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const size_t row = n / p.nx;
+        const int x = static_cast<int>(n - row * p.nx);
         double a[4][Q];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int i = 0; i < Q; ++i) a[k][i] = static_cast<double>(decode<MODE>(W[(k * Q + i) * N + n], k, i, p));
+            for (int i = 0; i < Q; ++i)
+                a[k][i] = static_cast<double>(decode<MODE>(W[fidx(Q, p.nx, row, k, i, x)], k, i, p));
         double rho[4] = {0.0, 0.0, 0.0, 0.0}, J[3] = {0.0, 0.0, 0.0}, K = 0.0;
         double nneg = 0.0, nbad = 0.0;
 #pragma unroll
@@ -81,22 +84,24 @@ k_spin_loss(const typename Store<MODE>::T* __restrict__ W, const double* __restr
     for (int s = 0; s < kRedSlots; ++s) acc[s] = 0.0;
     for (size_t n = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; n < N;
          n += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const size_t row = n / p.nx;
+        const int x = static_cast<int>(n - row * p.nx);
 #pragma unroll
         for (int k = 1; k < 4; ++k) {
             double r = 0.0;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) r += static_cast<double>(W[(k * Q + i) * N + n]);
+            for (int i = 0; i < Q; ++i) r += static_cast<double>(W[fidx(Q, p.nx, row, k, i, x)]);
             const double diff = r - rt[(k - 1) * N + n];
             acc[0] += diff * diff;
             if (lam) {
                 const T s = static_cast<T>(g * diff);
 #pragma unroll
-                for (int i = 0; i < Q; ++i) lam[(k * Q + i) * N + n] = s;
+                for (int i = 0; i < Q; ++i) lam[fidx(Q, p.nx, row, k, i, x)] = s;
             }
         }
         if (lam) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) lam[i * N + n] = T(0);
+            for (int i = 0; i < Q; ++i) lam[fidx(Q, p.nx, row, 0, i, x)] = T(0);
         }
     }
     block_reduce_store<0u>(acc, partials + blockIdx.x * kRedSlots);

@@ -126,7 +126,11 @@ class Handle:
 
     @property
     def field_shape(self):
-        return (4, self.Q) + self.grid
+        """Library layout: [ny, 4, Q, nx] (2D) or [nz, ny, 4, Q, nx] (3D)."""
+        i = self.info
+        if i["d"] == 2:
+            return (i["ny"], 4, self.Q, i["nx"])
+        return (i["nz"], i["ny"], 4, self.Q, i["nx"])
 
     @property
     def field_dtype(self):
@@ -137,6 +141,17 @@ class Handle:
     def empty_field(self, device="cuda"):
         import torch
         return torch.empty(self.field_shape, dtype=self.field_dtype, device=device)
+
+    def pauli_view(self, W):
+        """View of a field as [4, Q, *grid] (Pauli component, velocity, cells); no copy."""
+        return W.permute(1, 2, 0, 3) if self.info["d"] == 2 else W.permute(2, 3, 0, 1, 4)
+
+    def field_from_pauli(self, a, device="cuda"):
+        """Contiguous field in the library layout from values shaped [4, Q, *grid]."""
+        import torch
+        t = torch.as_tensor(a)
+        t = t.permute(2, 0, 1, 3) if self.info["d"] == 2 else t.permute(2, 3, 0, 1, 4)
+        return t.to(device=device, dtype=self.field_dtype).contiguous()
 
 
 def _info_dict(h_ptr):

@@ -46,8 +46,14 @@ def oracle_init(shape, fields, beta0=1.0):
     return lat, W
 
 
-def to_pauli_np(t):
-    return t.detach().to(torch.float64).cpu().numpy()
+def to_pauli_np(h, t):
+    """Library field -> float64 NumPy array [4, Q, *grid]."""
+    return h.pauli_view(t.detach()).to(torch.float64).cpu().numpy()
+
+
+def from_pauli(h, a):
+    """[4, Q, *grid] values -> device field in the library layout and storage type."""
+    return h.field_from_pauli(np.ascontiguousarray(a))
 
 
 def oracle_pauli(W):

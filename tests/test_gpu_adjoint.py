@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import fields, gpu_init, make_handle, normwise_rel_err, oracle_init, oracle_pauli, to_pauli_np
+from helpers import fields, from_pauli, gpu_init, make_handle, normwise_rel_err, oracle_init, oracle_pauli, to_pauli_np
 from oracle import adjoint, pauli, qlbm
 from paper_1309_1656_amd import mlbm, synthetic
 from paper_1309_1656_amd.rollout import MLBMRollout
@@ -30,10 +30,10 @@ def test_adjoint_step_matches_oracle(shape):
     h = make_handle(shape, tau=0.7)
     lam0 = h.empty_field()
     dom = torch.full((1,), 0.25, dtype=torch.float64, device="cuda")
-    mlbm.mlbm_adjoint_step(h, torch.from_numpy(oracle_pauli(Wo)).cuda(), torch.from_numpy(lam1).cuda(), lam0, dom)
+    mlbm.mlbm_adjoint_step(h, from_pauli(h, oracle_pauli(Wo)), from_pauli(h, lam1), lam0, dom)
     L0, dom_o = adjoint.step_vjp(lat, Wo, pauli.matrix_from_pauli(2.0 * lam1), 0.7)
     ref = pauli.pauli_from_matrix(L0) / 2.0
-    assert normwise_rel_err(to_pauli_np(lam0), ref) < 1e-12
+    assert normwise_rel_err(to_pauli_np(h, lam0), ref) < 1e-12
     assert abs((dom.item() - 0.25) - dom_o) <= 1e-11 * abs(dom_o)
 
 
@@ -56,7 +56,7 @@ def test_rollout_gradient_matches_oracle(K):
     lat, Wo = oracle_init(shape, f)
     Lo, Lam0, dtau_o = adjoint.rollout_grad(lat, Wo, tau, steps, rt_np)
     assert abs(L / Lo - 1) < 1e-12
-    assert normwise_rel_err(to_pauli_np(gW), pauli.pauli_from_matrix(Lam0) / 2.0) < 1e-11
+    assert normwise_rel_err(to_pauli_np(h, gW), pauli.pauli_from_matrix(Lam0) / 2.0) < 1e-11
     assert abs(gtau / dtau_o - 1) < 1e-11
 
 
@@ -94,7 +94,7 @@ def test_f32_rollout_against_f64_oracle():
     L, gW, gtau = _loss_and_grad(h, W0, tau, steps, 20, torch.from_numpy(rt_np).cuda())
     lat, Wo = oracle_init(shape, f)
     Lo, Lam0, dtau_o = adjoint.rollout_grad(lat, Wo, tau, steps, rt_np)
-    gerr = normwise_rel_err(to_pauli_np(gW), pauli.pauli_from_matrix(Lam0) / 2.0)
+    gerr = normwise_rel_err(to_pauli_np(h, gW), pauli.pauli_from_matrix(Lam0) / 2.0)
     print(f"f32 rollout: loss rel err {abs(L / Lo - 1):.2e}, grad W0 {gerr:.2e}, grad tau {abs(gtau / dtau_o - 1):.2e}")
     assert abs(L / Lo - 1) < 1e-5
     assert gerr < 1e-4
@@ -114,6 +114,6 @@ def test_spin_loss_matches_oracle():
     Lo, Lam = adjoint.spin_loss(lat, Wo, rt_np)
     assert abs(loss.item() / Lo - 1) < 1e-13
     ref = pauli.pauli_from_matrix(Lam) / 2.0
-    got = to_pauli_np(lam)
+    got = to_pauli_np(h, lam)
     assert np.all(got[0] == 0)
     assert np.max(np.abs(got[1:] - ref[1:])) <= 1e-13 * np.abs(ref[1:]).max()

@@ -1,0 +1,196 @@
+"""Full-size workloads in the launch configuration the benchmark times.
+
+For each workload:
+* global conserved averages (Eqs. GlobalDensity, GlobalVelocity,
+  GlobalTotalEnergy) stay constant over the whole run;
+* the last step is checked cell by cell at sampled cells against one oracle
+  step computed from the GPU's own state before it (the oracle collides the
+  Q neighbour cells x - c_i and streams population i to x);
+* where a stored oracle run exists (tests/golden/oracle_<name>.npz, written
+  by tests/golden/make_oracle_runs.py), the final state is compared with it at
+  the stored cells: F64 within 1e-12, F32 within 1e-5 (normwise: max error
+  over the sampled populations / max |a_k| over the whole field).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import dims_of, make_handle
+from oracle import pauli, qlbm
+from paper_1309_1656_amd import mlbm, synthetic
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+B = synthetic.BASE_SEED
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _inputs(h, f):
+    to = lambda a: (a if torch.is_tensor(a) else torch.from_numpy(np.ascontiguousarray(a))).to(
+        device="cuda", dtype=torch.float64).contiguous()
+    rho4 = torch.cat([to(f["trrho"])[None], to(f["r"])])
+    return rho4, to(f["u_lat"]) * h.info["xi"], to(f["T"])
+
+
+def _cells(shape, flat):
+    return np.unravel_index(flat, shape)
+
+
+def sampled_step_error(h, W_before, W_after, tau, ncheck=512, seed=0):
+    """Normwise error of one GPU step at sampled cells against the oracle."""
+    shape = h.grid
+    d = len(shape)
+    lat = qlbm.Lattice(d, h.info["beta0"])
+    Q = lat.Q
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(int(np.prod(shape)), ncheck, replace=False)
+    coords = _cells(shape, flat)
+    # neighbour x - c_i of every sampled cell, per array axis (axis ax <-> component d-1-ax)
+    nb = [(coords[ax][:, None] - lat.c[None, :, d - 1 - ax]) % shape[ax] for ax in range(d)]
+    view_b = h.pauli_view(W_before)
+    idx = tuple(torch.from_numpy(a.reshape(-1)).cuda() for a in nb)
+    a = view_b[(slice(None), slice(None)) + idx].to(torch.float64).cpu().numpy()   # [4, Q, M*Q]
+    if h.info["storage"] == mlbm.MLBM_STORE_F16DEV:
+        raise ValueError("sampled check needs F64 or F32 storage")
+    coll = pauli.pauli_from_matrix(qlbm.collide(lat, pauli.matrix_from_pauli(a), tau))
+    coll = coll.reshape(4, Q, ncheck, Q)
+    expect = np.diagonal(coll, axis1=1, axis2=3).transpose(0, 2, 1)                # [4, Q, M]
+    idx_self = tuple(torch.from_numpy(c).cuda() for c in coords)
+    got = h.pauli_view(W_after)[(slice(None), slice(None)) + idx_self].to(torch.float64).cpu().numpy()
+    return max(np.abs(got[k] - expect[k]).max() / np.abs(expect[k]).max() for k in range(4))
+
+
+def golden_error(h, W, name):
+    path = os.path.join(GOLDEN, f"oracle_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    coords = _cells(h.grid, g["cells"])
+    idx = tuple(torch.from_numpy(c).cuda() for c in coords)
+    got = h.pauli_view(W)[(slice(None), slice(None)) + idx].to(torch.float64).cpu().numpy()
+    ref = g["values"]
+    return max(np.abs(got[k] - ref[k]).max() / g["maxabs"][k] for k in range(4))
+
+
+def golden_rho_error(h, W, name):
+    """F16 deviation storage: compare the density matrices at the stored cells."""
+    path = os.path.join(GOLDEN, f"oracle_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    rho4 = torch.empty((4,) + tuple(h.grid), dtype=torch.float64, device="cuda")
+    mlbm.mlbm_moments(h, W, rho4=rho4)
+    coords = _cells(h.grid, g["cells"])
+    idx = tuple(torch.from_numpy(c).cuda() for c in coords)
+    got = rho4[(slice(None),) + idx].cpu().numpy()
+    ref = g["values"].sum(axis=1)
+    return max(np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max() for k in range(4))
+
+
+def run_workload(shape, tau, steps, f, storage, name=None, sampled=True):
+    h = make_handle(shape, tau=tau, storage=storage)
+    W = h.empty_field()
+    mlbm.mlbm_init_equilibrium(h, W, *_inputs(h, f))
+    g0, _ = mlbm.mlbm_moments(h, W)
+    scratch = h.empty_field()
+    mlbm.mlbm_step(h, W, scratch, steps - 1)
+    Wb = W.clone() if sampled else None
+    mlbm.mlbm_step(h, W, scratch, 1)
+    g1, nneg = mlbm.mlbm_moments(h, W)
+    out = {"drift": float(np.abs(g1 - g0).max() / np.abs(g0).max()), "n_neg": nneg}
+    if sampled:
+        out["step"] = sampled_step_error(h, Wb, W, tau)
+    if name is not None:
+        out["golden"] = golden_error(h, W, name) if storage != mlbm.MLBM_STORE_F16DEV else golden_rho_error(h, W, name)
+    _log(f"{name or shape} storage={storage}: {out}")
+    return h, W, out
+
+
+@pytest.mark.parametrize("storage", [mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32, mlbm.MLBM_STORE_F16DEV])
+def test_d3q19_128(storage):
+    """D3Q19 128^3, tau 0.8, 500 steps: the benchmark workload."""
+    shape = (128, 128, 128)
+    f = synthetic.macroscopic_fields(shape, B + 3)
+    _, _, r = run_workload(shape, 0.8, 500, f, storage, "d3q19_128_tau0.8_500",
+                           sampled=storage != mlbm.MLBM_STORE_F16DEV)
+    if storage == mlbm.MLBM_STORE_F64:
+        assert r["drift"] < 1e-12 and r["step"] < 1e-13
+        assert r["golden"] is None or r["golden"] < 1e-12
+    elif storage == mlbm.MLBM_STORE_F32:
+        assert r["step"] < 1e-6
+        assert r["golden"] is None or r["golden"] < 1e-5
+    else:
+        assert r["golden"] is None or r["golden"] < 5e-3
+
+
+@pytest.mark.parametrize("storage", [mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32, mlbm.MLBM_STORE_F16DEV])
+def test_d3q19_64_subrun(storage):
+    """The 64^3 sub-run of the 384^3 workload family, 200 steps, against the stored oracle run."""
+    shape = (64, 64, 64)
+    f = synthetic.macroscopic_fields(shape, B + 4)
+    _, _, r = run_workload(shape, 0.8, 200, f, storage, "d3q19_64_tau0.8_200",
+                           sampled=storage != mlbm.MLBM_STORE_F16DEV)
+    assert r["golden"] is not None, "stored oracle run missing"
+    bar = {mlbm.MLBM_STORE_F64: 1e-12, mlbm.MLBM_STORE_F32: 1e-5, mlbm.MLBM_STORE_F16DEV: 5e-3}[storage]
+    assert r["golden"] < bar
+
+
+@pytest.mark.parametrize("storage", [mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32, mlbm.MLBM_STORE_F16DEV])
+def test_d3q19_384(storage):
+    """D3Q19 384^3, 200 steps: conservation and a sampled oracle step at full size."""
+    shape = (384, 384, 384)
+    f = synthetic.macroscopic_fields(shape, B + 4, device="cuda")
+    h, W, r = run_workload(shape, 0.8, 200, f, storage, None, sampled=storage != mlbm.MLBM_STORE_F16DEV)
+    del f
+    if storage == mlbm.MLBM_STORE_F64:
+        assert r["drift"] < 1e-12 and r["step"] < 1e-13
+    elif storage == mlbm.MLBM_STORE_F32:
+        assert r["step"] < 1e-6
+    del W, h
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.0])
+@pytest.mark.parametrize("storage", [mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32])
+def test_d2q9_1024_shear(tau, storage):
+    """D2Q9 1024^2 with the spin-polarised shear band, 1000 steps."""
+    shape = (1024, 1024)
+    f = synthetic.shear_band_fields(shape, B + 2)
+    _, _, r = run_workload(shape, tau, 1000, f, storage, f"d2q9_1024_shear_tau{tau}_1000")
+    if storage == mlbm.MLBM_STORE_F64:
+        assert r["drift"] < 1e-12 and r["step"] < 1e-13
+        assert r["golden"] is None or r["golden"] < 1e-12
+    else:
+        assert r["step"] < 1e-6
+        assert r["golden"] is None or r["golden"] < 1e-5
+
+
+def test_d2q9_512_rollout_f32_vs_f64():
+    """Differentiation workload: FP32 rollout (checkpoints every 20) against the FP64 one on the GPU."""
+    from paper_1309_1656_amd.rollout import MLBMRollout
+    wl = synthetic.WORKLOADS["d2q9_512_adjoint"]
+    shape, tau, steps = wl["shape"], wl["tau"], wl["steps"]
+    f = synthetic.macroscopic_fields(shape, wl["seed"])
+    rt = torch.from_numpy(synthetic.target_bloch_field(shape, wl["seed"] + 100)).cuda()
+    res = {}
+    for storage in (mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32):
+        h = make_handle(shape, tau=tau, storage=storage)
+        W0 = h.empty_field()
+        mlbm.mlbm_init_equilibrium(h, W0, *_inputs(h, f))
+        W0.requires_grad_(True)
+        tau_t = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+        loss = MLBMRollout.apply(W0, tau_t, h, steps, 20, rt)
+        loss.backward()
+        res[storage] = (loss.item(), h.pauli_view(W0.grad).double().cpu().numpy(), tau_t.grad.item())
+    l64, g64, t64 = res[mlbm.MLBM_STORE_F64]
+    l32, g32, t32 = res[mlbm.MLBM_STORE_F32]
+    gerr = max(np.abs(g32[k] - g64[k]).max() / np.abs(g64[k]).max() for k in range(4))
+    _log(f"512^2 rollout: loss {l64:.6e} rel diff {abs(l32 / l64 - 1):.2e}; grad W0 {gerr:.2e}; "
+         f"grad tau {t64:.6e} rel diff {abs(t32 / t64 - 1):.2e}")
+    assert np.isfinite(g32).all() and abs(l32 / l64 - 1) < 1e-5 and gerr < 1e-4 and abs(t32 / t64 - 1) < 1e-4

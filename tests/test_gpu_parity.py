@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import (device_inputs, fields, gpu_init, make_handle, normwise_rel_err, oracle_init,
+from helpers import (device_inputs, fields, from_pauli, gpu_init, make_handle, normwise_rel_err, oracle_init,
                      oracle_pauli, to_pauli_np)
 from oracle import pauli, qlbm
 from paper_1309_1656_amd import mlbm
@@ -36,9 +36,9 @@ def test_stream_bit_exact(shape, storage):
     mlbm.mlbm_stream(h, src, dst)
     torch.cuda.synchronize()
     lat = qlbm.Lattice(len(shape))
-    raw = src.cpu().numpy()
+    raw = h.pauli_view(src).cpu().numpy()
     expect = np.stack([qlbm.stream(lat, raw[k][..., None, None])[..., 0, 0] for k in range(4)])
-    got = dst.cpu().numpy()
+    got = np.ascontiguousarray(h.pauli_view(dst).cpu().numpy())
     assert got.dtype == expect.dtype
     assert np.array_equal(got.view(np.uint8), expect.view(np.uint8))
 
@@ -48,7 +48,7 @@ def test_init_matches_oracle(shape):
     _flush(f"init {shape}")
     f = fields(shape, 21)
     h = make_handle(shape)
-    W = to_pauli_np(gpu_init(h, f))
+    W = to_pauli_np(h, gpu_init(h, f))
     _, Wo = oracle_init(shape, f)
     assert normwise_rel_err(W, oracle_pauli(Wo)) < 1e-13
 
@@ -63,7 +63,7 @@ def test_init_degenerate_states_use_quadrature_branch():
         f["r"] = f["r"] / np.abs(f["r"]).max() * 1.5
         f["T"] = 0.3 + 0.5 * (f["T"] - 1.0)
         h = make_handle(shape)
-        W = to_pauli_np(gpu_init(h, f))
+        W = to_pauli_np(h, gpu_init(h, f))
         lat, Wo = oracle_init(shape, f)
         _, nu_up, nu_dn, _ = qlbm.fd_parameters(lat.d, f["trrho"], f["r"], f["T"])
         assert nu_up.max() > 0.0     # degenerate regime reached
@@ -84,10 +84,10 @@ def test_collide_matches_oracle(shape, inplace):
     lat, Wo = oracle_init(shape, f)
     Wo = _perturbed(lat, Wo)
     h = make_handle(shape, tau=0.7)
-    src = torch.from_numpy(oracle_pauli(Wo)).cuda()
+    src = from_pauli(h, oracle_pauli(Wo))
     dst = src if inplace else h.empty_field()
     mlbm.mlbm_collide(h, src, dst)
-    got = to_pauli_np(dst)
+    got = to_pauli_np(h, dst)
     assert normwise_rel_err(got, oracle_pauli(qlbm.collide(lat, Wo, 0.7))) < 1e-14
 
 
@@ -101,7 +101,7 @@ def test_multi_step_f64(shape, steps, tau):
     mlbm.mlbm_step(h, W, h.empty_field(), steps)
     lat, Wo = oracle_init(shape, f)
     ref = oracle_pauli(qlbm.run(lat, Wo, tau, steps))
-    assert normwise_rel_err(to_pauli_np(W), ref) < 1e-12
+    assert normwise_rel_err(to_pauli_np(h, W), ref) < 1e-12
 
 
 @pytest.mark.parametrize("shape,steps", [((64, 64), 100), ((13, 9, 11), 40)])
@@ -112,7 +112,7 @@ def test_multi_step_f32(shape, steps):
     W = gpu_init(h, f)
     mlbm.mlbm_step(h, W, h.empty_field(), steps)
     lat, Wo = oracle_init(shape, f)
-    err = normwise_rel_err(to_pauli_np(W), oracle_pauli(qlbm.run(lat, Wo, 0.8, steps)))
+    err = normwise_rel_err(to_pauli_np(h, W), oracle_pauli(qlbm.run(lat, Wo, 0.8, steps)))
     _flush(f"  f32 max rel err {err:.3e}")
     assert err < 1e-5
 
@@ -142,7 +142,7 @@ def test_moments_match_oracle(shape):
     lat, Wo = oracle_init(shape, f)
     Wo = _perturbed(lat, Wo, amp=0.3)
     h = make_handle(shape)
-    W = torch.from_numpy(oracle_pauli(Wo)).cuda()
+    W = from_pauli(h, oracle_pauli(Wo))
     d = len(shape)
     rho4 = torch.empty((4,) + tuple(shape), dtype=torch.float64, device="cuda")
     u = torch.empty((d,) + tuple(shape), dtype=torch.float64, device="cuda")
@@ -162,7 +162,7 @@ def test_nonfinite_is_reported():
     shape = (16, 16)
     h = make_handle(shape)
     W = gpu_init(h, fields(shape, 3))
-    W[0, 3, 5, 7] = float("nan")
+    W[3, 0, 5, 7] = float("nan")
     with pytest.raises(mlbm.MlbmError) as e:
         mlbm.mlbm_moments(h, W)
     assert e.value.code == mlbm.MLBM_ENONFINITE
@@ -210,17 +210,17 @@ def test_eigen_mode_equals_direct_and_oracle():
         mlbm.mlbm_step(h, W, h.empty_field(), steps)
         mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_EIGEN)
         mlbm.mlbm_step(h, We, h.empty_field(), steps)
-        a, b = to_pauli_np(W), to_pauli_np(We)
+        a, b = to_pauli_np(h, W), to_pauli_np(h, We)
         assert normwise_rel_err(b, a) < 1e-12
         # one eigen-mode collision against the oracle's eigen route
         from oracle import eigen
         lat, Wo = oracle_init(shape, f)
         Wo = _perturbed(lat, Wo)
-        src = torch.from_numpy(oracle_pauli(Wo)).cuda()
+        src = from_pauli(h, oracle_pauli(Wo))
         dst = h.empty_field()
         mlbm.mlbm_collide(h, src, dst)
         ref = Wo + (1.0 / 0.8) * (eigen.equilibrium_eigen(lat, Wo) - Wo)
-        assert normwise_rel_err(to_pauli_np(dst), oracle_pauli(ref)) < 1e-12
+        assert normwise_rel_err(to_pauli_np(h, dst), oracle_pauli(ref)) < 1e-12
 
 
 def test_resume_is_bitwise():
