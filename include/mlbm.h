@@ -33,15 +33,21 @@
  * [rows][N] with cell = x + nx * (y + ny * z).  Storage types:
  *   MLBM_STORE_F64     double; all arithmetic in double.
  *   MLBM_STORE_F32     float; collision arithmetic in float, moment sums in
- *                      double.
- *   MLBM_STORE_F16DEV  IEEE binary16 h = (a - R_ki) / (w_i S), the scaled
+ *                      double.  The conservation defect of each cell's
+ *                      rounded outputs (mass per Pauli component, momentum,
+ *                      energy) is summed in double and folded back into the
+ *                      rest and axis populations, so the rounding of the float
+ *                      constants does not make the global averages drift.
+ *   MLBM_STORE_F16DEV  IEEE binary16 h = (a - R_ki) / s_i, the scaled
  *                      deviation from a lattice-weighted reference
  *                      equilibrium R_ki = w_i rho_bar_k P_i(u_bar, eps_bar) of
- *                      the global means of the initial state, with a global
- *                      power-of-two scale S; both are fixed by
- *                      mlbm_init_equilibrium and kept in the handle.  Encoding
- *                      rounds to nearest even; arithmetic in float, moment sums
- *                      in double.
+ *                      the global means of the initial state.  S is the power
+ *                      of two at or above max |a - R| / w_i over the initial
+ *                      field, and s_i = 2^round(log2(w_i S)) (|h| <= sqrt 2
+ *                      initially; both scalings are exact).  R and S are fixed
+ *                      by mlbm_init_equilibrium and kept in the handle.
+ *                      Encoding rounds to nearest even; arithmetic in float,
+ *                      moment sums in double.
  *
  * Time stepping (Sec. 3.3): Delta t = 1, Delta x = xi, omega = 1/tau.  One step
  * computes per cell the moments rho, u, eps (Eq. DiscrAvr), the polynomial

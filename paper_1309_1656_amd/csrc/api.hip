@@ -87,9 +87,11 @@ void set_f16(mlbm_ctx* h, const double* ref, double scale) {
             h->f16_ref[k][i] = ref[k * h->Q + i];
             h->kp.ref[k][i] = static_cast<float>(ref[k * h->Q + i]);
         }
+    // per-velocity scale: the power of two nearest to w_i S (so |h| <= sqrt(2) max|a - R|/(w_i S))
     for (int i = 0; i < h->Q; ++i) {
-        h->kp.wS[i] = static_cast<float>(h->kp.w[i] * scale);
-        h->kp.inv_wS[i] = static_cast<float>(1.0 / (h->kp.w[i] * scale));
+        const int e = static_cast<int>(std::lround(std::log2(h->kp.w[i] * scale)));
+        h->kp.sc[i] = std::ldexp(1.0f, e);
+        h->kp.inv_sc[i] = std::ldexp(1.0f, -e);
     }
 }
 
@@ -202,7 +204,7 @@ int mlbm_create(mlbm_handle* out, int lattice, const int64_t dims[3], double tau
     set_tau(h, tau);
     for (int k = 0; k < 4; ++k)
         for (int i = 0; i < 19; ++i) p.ref[k][i] = 0.0f;
-    for (int i = 0; i < 19; ++i) p.wS[i] = p.inv_wS[i] = 1.0f;
+    for (int i = 0; i < 19; ++i) p.sc[i] = p.inv_sc[i] = 1.0f;
     gauss_legendre(kGL, h->fp.gl_x, h->fp.gl_w);
     *out = h;
     return ok();

@@ -58,10 +58,10 @@ struct KParams {
     double omw[19];            // omega * w_i
     float omwf[19];
     float one_m_omf, a3f, a4f;
-    // F16 scaled-deviation codec: a = ref[k][i] + wS[i] * h
+    // F16 scaled-deviation codec: a = ref[k][i] + sc[i] * h, sc[i] a power of two
     float ref[4][19];
-    float wS[19];
-    float inv_wS[19];
+    float sc[19];
+    float inv_sc[19];
 };
 
 template <int MODE> struct Store;
@@ -73,19 +73,22 @@ template <int MODE>
 __device__ __forceinline__ typename Store<MODE>::C decode(typename Store<MODE>::T v, int k, int i,
                                                           const KParams& p) {
     if constexpr (MODE == kF16Dev) {
-        return p.ref[k][i] + p.wS[i] * static_cast<float>(v);
+        return p.ref[k][i] + p.sc[i] * static_cast<float>(v);
     } else {
         (void)k; (void)i; (void)p;
         return v;
     }
 }
 
-// Round to the storage type: round-to-nearest-even in every mode.
+// Round to the storage type: round-to-nearest-even in every mode.  The F16
+// scale of each velocity is a power of two, so scaling by it and by its
+// inverse is exact and decode(encode(v)) differs from v only by the
+// half-precision rounding of the deviation (no systematic gain).
 template <int MODE>
 __device__ __forceinline__ typename Store<MODE>::T encode(typename Store<MODE>::C v, int k, int i,
                                                           const KParams& p) {
     if constexpr (MODE == kF16Dev) {
-        return static_cast<_Float16>((v - p.ref[k][i]) * p.inv_wS[i]);
+        return static_cast<_Float16>((v - p.ref[k][i]) * p.inv_sc[i]);
     } else {
         (void)k; (void)i; (void)p;
         return v;

@@ -23,6 +23,47 @@
 
 namespace mlbm {
 
+// FP32 storage: the float constants (omega w_i, 1 - omega, the Appendix
+// coefficients) carry fixed rounding errors, so an uncorrected float
+// collision gains or loses a fixed ~1e-8 of the conserved moments every step
+// and the global averages drift.  (With FP16 storage the half-precision
+// quantisation of the deviations dominates instead, so the correction is not
+// applied there.)  The defect of the rounded outputs is summed
+// in double and folded back exactly:
+//   every channel k: mass sum_i (S_ik - a_ik) is removed from the rest population;
+//   trace channel: momentum component d is removed through the axis pair
+//   (+d, -d) (opposite halves: mass and energy unchanged), and energy through
+//   the rest and the 2D axis populations (+dE on the rest, -dE/(2D) on each
+//   axis population: mass and momentum unchanged).
+// Afterwards the conserved moments of S equal those of a up to one final float
+// rounding per value, which has no preferred sign.
+template <int Q, typename C>
+__device__ __forceinline__ void conserve(C (&S)[Q], const C (&a)[Q], int k) {
+    constexpr int D = Lat<Q>::D;
+    double dm = 0.0, dj[3] = {0.0, 0.0, 0.0}, dE = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double dd = static_cast<double>(S[i]) - static_cast<double>(a[i]);
+        dm += dd;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dj[c] += Lat<Q>::c(i, c) * dd;
+        dE += csq<Q>(i) * dd;
+    }
+    if (k != 0) {
+        S[0] = static_cast<C>(static_cast<double>(S[0]) - dm);
+        return;
+    }
+    S[0] = static_cast<C>(static_cast<double>(S[0]) - dm + dE);
+    const double de_axis = dE / (2 * D);
+#pragma unroll
+    for (int i = 1; i <= 2 * D; ++i) {
+        // axis velocities 1..2D come in pairs (+d, -d); i odd is +d
+        const int dim = (i - 1) / 2;
+        const double sgn = (i & 1) ? -0.5 : 0.5;
+        S[i] = static_cast<C>(static_cast<double>(S[i]) - de_axis + sgn * dj[dim]);
+    }
+}
+
 template <int Q, int MODE, bool PULL, bool COLL, int BX>
 __global__ void __launch_bounds__(BX * 4)
 k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T* __restrict__ dst,
@@ -120,10 +161,13 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
         // collision (Eq. CollisionStep) of this wave's channel
         const C r = static_cast<C>(rk);
         const C omm = cst<C>(p.one_m_om, p.one_m_omf);
+        C S[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) S[i] = omm * a[i] + qs[i][lx] * r;
+        if constexpr (MODE == kF32) conserve<Q>(S, a, k);
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            __builtin_nontemporal_store(encode<MODE>(omm * a[i] + qs[i][lx] * r, k, i, p),
-                                        dst + fidx(Q, nx, row, k, i, x));
+            __builtin_nontemporal_store(encode<MODE>(S[i], k, i, p), dst + fidx(Q, nx, row, k, i, x));
     }
 }
 

@@ -123,9 +123,11 @@ def test_d3q19_128(storage):
         assert r["drift"] < 1e-12 and r["step"] < 1e-13
         assert r["golden"] is None or r["golden"] < 1e-12
     elif storage == mlbm.MLBM_STORE_F32:
-        assert r["step"] < 1e-6
+        assert r["drift"] < 1e-8 and r["step"] < 1e-6
         assert r["golden"] is None or r["golden"] < 1e-5
     else:
+        # half-precision rounding near a steady state repeats from step to step
+        assert r["drift"] < 1e-4
         assert r["golden"] is None or r["golden"] < 5e-3
 
 
@@ -151,7 +153,9 @@ def test_d3q19_384(storage):
     if storage == mlbm.MLBM_STORE_F64:
         assert r["drift"] < 1e-12 and r["step"] < 1e-13
     elif storage == mlbm.MLBM_STORE_F32:
-        assert r["step"] < 1e-6
+        assert r["drift"] < 1e-8 and r["step"] < 1e-6
+    else:
+        assert r["drift"] < 1e-4
     del W, h
     torch.cuda.empty_cache()
 
@@ -167,7 +171,7 @@ def test_d2q9_1024_shear(tau, storage):
         assert r["drift"] < 1e-12 and r["step"] < 1e-13
         assert r["golden"] is None or r["golden"] < 1e-12
     else:
-        assert r["step"] < 1e-6
+        assert r["drift"] < 1e-8 and r["step"] < 1e-6
         assert r["golden"] is None or r["golden"] < 1e-5
 
 
