@@ -88,6 +88,7 @@ typedef struct mlbm_ctx* mlbm_handle;
 enum { MLBM_D2Q9 = 9, MLBM_D3Q19 = 19 };
 enum { MLBM_STORE_F64 = 0, MLBM_STORE_F32 = 1, MLBM_STORE_F16DEV = 2 };
 enum { MLBM_EQ_DIRECT = 0, MLBM_EQ_EIGEN = 1 };
+enum { MLBM_ORDER_AUTO = -1, MLBM_ORDER_NATURAL = 0, MLBM_ORDER_XCD_RANGE = 1, MLBM_ORDER_INTERLEAVE8 = 2 };
 enum {
     MLBM_OK = 0,
     MLBM_EINVAL = -1,     /* bad argument: null pointer, bad enum, bad size   */
@@ -115,6 +116,8 @@ typedef struct {
     /* Appendix coefficients: alpha1 = a1_0 + a1_b b, alpha2 = a2_0 + a2_b b,
      * b = beta0 eps; alpha3..alpha5 constant.                                 */
     double a1_0, a1_b, a2_0, a2_b, a3, a4, a5;
+    int launch_block_x;   /* step kernels: cells per workgroup along x (64, 128) */
+    int launch_order;     /* step kernels: block order (MLBM_ORDER_*)          */
     double f16_scale;     /* S of MLBM_STORE_F16DEV (0 before initialisation) */
     double f16_ref[4][19];/* R_ki of MLBM_STORE_F16DEV                          */
 } mlbm_info;
@@ -259,6 +262,19 @@ int mlbm_spin_loss(mlbm_handle h, const void* W, const double* r_target,
  */
 int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next,
                       void* lam_n, double* dL_domega, void* stream);
+
+/*
+ * mlbm_set_launch -- launch shape of the step kernels (performance only; the
+ * results are identical).  Each workgroup covers block_x consecutive cells
+ * of one x-row with four waves per 64 cells, one per Pauli component
+ * (block_x = 64 or 128; 0 = automatic).  order chooses how workgroups map to
+ * the 8 XCDs of the chip, each with its own L2 (MLBM_ORDER_NATURAL: x-chunk
+ * fastest; MLBM_ORDER_XCD_RANGE: a contiguous range of rows per XCD;
+ * MLBM_ORDER_INTERLEAVE8: 8 rows across the XCDs, the chunks of a row on one
+ * XCD; MLBM_ORDER_AUTO: chosen from the grid size and storage type).
+ * mlbm_get_info reports the shape in effect.  Errors: MLBM_EINVAL.
+ */
+int mlbm_set_launch(mlbm_handle h, int block_x, int order);
 
 /*
  * mlbm_set_f16_reference -- restore the MLBM_STORE_F16DEV reference R (4*Q

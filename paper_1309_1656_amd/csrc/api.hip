@@ -27,6 +27,7 @@ struct mlbm_ctx {
     FdParams fp{};
     double f16_scale = 0.0;
     double f16_ref[4][19] = {};
+    LaunchCfg launch;               // step launch shape (automatic by default)
     int device = -1;
     double* d_partials = nullptr;   // reduction partials
     size_t partials_cap = 0;        // in doubles
@@ -245,6 +246,10 @@ int mlbm_get_info(mlbm_handle h, mlbm_info* info) {
     info->a3 = h->kp.a3;
     info->a4 = h->kp.a4;
     info->a5 = h->kp.a5;
+    const LaunchCfg lc = step_launch(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz),
+                                     h->Q, h->storage, h->launch);
+    info->launch_block_x = lc.bx;
+    info->launch_order = lc.order;
     info->f16_scale = h->f16_scale;
     for (int k = 0; k < 4; ++k)
         for (int i = 0; i < h->Q; ++i) info->f16_ref[k][i] = h->f16_ref[k][i];
@@ -271,6 +276,15 @@ int mlbm_set_eq_mode(mlbm_handle h, int mode) {
     if (mode == MLBM_EQ_EIGEN && h->storage != MLBM_STORE_F64)
         return fail(MLBM_EINVAL, "the eigen-channel mode needs double storage");
     h->eq_mode = mode;
+    return ok();
+}
+
+int mlbm_set_launch(mlbm_handle h, int block_x, int order) {
+    if (int e = check_handle(h)) return e;
+    if (block_x != 0 && block_x != 64 && block_x != 128) return fail(MLBM_EINVAL, "block_x must be 0, 64 or 128");
+    if (order < -1 || order > 2) return fail(MLBM_EINVAL, "order must be -1, 0, 1 or 2");
+    h->launch.bx = block_x;
+    h->launch.order = order;
     return ok();
 }
 
@@ -340,7 +354,7 @@ int mlbm_step(mlbm_handle h, void* W, void* scratch, int nsteps, void* stream) {
     const bool eig = h->eq_mode == MLBM_EQ_EIGEN;
     auto run = [&](StepKind kind, const void* a, void* b) -> hipError_t {
         if (eig && kind != StepKind::StreamOnly) return launch_step_eigen(kind, h->Q, a, b, h->kp, h->fp, nullptr, s);
-        return launch_step(kind, h->Q, h->storage, a, b, h->kp, s);
+        return launch_step(kind, h->Q, h->storage, a, b, h->kp, h->launch, s);
     };
     // After the collide-only pass and nsteps - 1 fused passes the
     // post-collision state sits in `scratch`; the stream-only pass then
@@ -363,7 +377,7 @@ int mlbm_collide(mlbm_handle h, const void* src, void* dst, void* stream) {
     if (!src || !dst) return fail(MLBM_EINVAL, "null field");
     hipStream_t s = as_stream(stream);
     if (h->eq_mode == MLBM_EQ_EIGEN) HIP_TRY(launch_step_eigen(StepKind::CollideOnly, h->Q, src, dst, h->kp, h->fp, nullptr, s));
-    else HIP_TRY(launch_step(StepKind::CollideOnly, h->Q, h->storage, src, dst, h->kp, s));
+    else HIP_TRY(launch_step(StepKind::CollideOnly, h->Q, h->storage, src, dst, h->kp, h->launch, s));
     return ok();
 }
 
@@ -371,7 +385,7 @@ int mlbm_stream(mlbm_handle h, const void* src, void* dst, void* stream) {
     if (int e = check_handle(h)) return e;
     if (!src || !dst) return fail(MLBM_EINVAL, "null field");
     if (src == dst) return fail(MLBM_EINVAL, "streaming needs distinct src and dst");
-    HIP_TRY(launch_step(StepKind::StreamOnly, h->Q, h->storage, src, dst, h->kp, as_stream(stream)));
+    HIP_TRY(launch_step(StepKind::StreamOnly, h->Q, h->storage, src, dst, h->kp, h->launch, as_stream(stream)));
     return ok();
 }
 

@@ -9,6 +9,15 @@ namespace mlbm {
 
 enum class StepKind { Fused, CollideOnly, StreamOnly };
 
+// Launch shape of the step kernels: cells per workgroup along x (64 or 128;
+// 0 = automatic) and block order (-1 = automatic).
+enum { kOrderNatural = 0, kOrderXcdRange = 1, kOrderInterleave8 = 2 };
+struct LaunchCfg {
+    int bx = 0;
+    int order = -1;
+};
+LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want);
+
 // Gauss-Legendre rule on [-1, 1] used by the device Fermi-Dirac integrals.
 constexpr int kGL = 20;
 struct FdParams {
@@ -17,7 +26,7 @@ struct FdParams {
 };
 
 hipError_t launch_step(StepKind kind, int Q, int mode, const void* src, void* dst, const KParams& p,
-                       hipStream_t s);
+                       LaunchCfg want, hipStream_t s);
 
 // Eigen-channel variant of the fused / collide-only pass (double storage only).
 hipError_t launch_step_eigen(StepKind kind, int Q, const void* src, void* dst, const KParams& p,

@@ -64,10 +64,49 @@ __device__ __forceinline__ void conserve(C (&S)[Q], const C (&a)[Q], int k) {
     }
 }
 
+// Block order.  The grid is one-dimensional and the hardware hands block b to
+// XCD b mod 8 (round robin); each XCD has its own L2.  Blocks that cover
+// neighbouring x-chunks of one row read the same boundary cache lines (the
+// x-shifted pulls).  Three bijections of [0, gridDim.x) onto (chunk, row):
+//   kOrderNatural     chunk fastest, rows in order;
+//   kOrderXcdRange    every XCD runs one contiguous range of logical blocks,
+//                     so the chunks of a row share an L2;
+//   kOrderInterleave8 8 consecutive rows go to the 8 XCDs and the chunks of a
+//                     row follow 8 blocks apart on the same XCD; rows are
+//                     still swept in order across the chip.
+// Which is fastest depends on the grid (measured on MI355X; see step_launch).
+__device__ __forceinline__ void block_order(int order, int nx, int ny, int bx, int& chunk, int& y, int& z) {
+    constexpr unsigned kXcd = 8;
+    const unsigned b = blockIdx.x, G = gridDim.x;
+    const unsigned nchunk = (static_cast<unsigned>(nx) + bx - 1) / bx;
+    unsigned row, ch;
+    if (order == kOrderInterleave8) {
+        const unsigned grp = kXcd * nchunk, g = b / grp, t = b % grp;
+        if (g < G / grp) {
+            ch = t / kXcd;
+            row = g * kXcd + t % kXcd;
+        } else {          // last, partial group of rows: natural order
+            ch = t % nchunk;
+            row = g * kXcd + t / nchunk;
+        }
+    } else {
+        unsigned L = b;
+        if (order == kOrderXcdRange) {
+            const unsigned q = G / kXcd, r = G % kXcd, j = b % kXcd;
+            L = j * q + (j < r ? j : r) + b / kXcd;
+        }
+        row = L / nchunk;
+        ch = L - row * nchunk;
+    }
+    chunk = static_cast<int>(ch);
+    y = static_cast<int>(row % static_cast<unsigned>(ny));
+    z = static_cast<int>(row / static_cast<unsigned>(ny));
+}
+
 template <int Q, int MODE, bool PULL, bool COLL, int BX>
 __global__ void __launch_bounds__(BX * 4)
 k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T* __restrict__ dst,
-       const KParams p) {
+       const KParams p, const int order) {
     using T = typename Store<MODE>::T;
     using C = typename Store<MODE>::C;
     constexpr int D = Lat<Q>::D;
@@ -75,9 +114,10 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
 
     const int lx = threadIdx.x;
     const int k = __builtin_amdgcn_readfirstlane(threadIdx.y);   // Pauli channel, uniform per wave
-    const int x = blockIdx.x * BX + lx;
-    const int y = blockIdx.y, z = blockIdx.z;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
+    int chunk, y, z;
+    block_order(order, nx, ny, BX, chunk, y, z);
+    const int x = chunk * BX + lx;
     const bool active = x < nx;
     const int xx = active ? x : nx - 1;
     const size_t row = static_cast<size_t>(z) * ny + y;
@@ -171,49 +211,62 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
     }
 }
 
-// Cells per workgroup along x (4 waves per 64 cells).  Chosen from
-// measurements on MI355X: 64 for double storage on rows of at most 128 cells,
-// otherwise 128; rows shorter than 128 cells always take 64.
-static int step_bx(int nx, int mode) {
-    if (nx <= 64) return 64;
-    if (mode == kF64 && nx <= 128) return 64;
-    return 128;
+// Launch shape (cells per workgroup along x, block order) when the handle
+// does not fix one, from sweeps of all six shapes on MI355X:
+//   D2Q9 (rows of >= 128 cells): 128-cell blocks, 8-row interleave
+//     (1024^2: 5.9-6.0 TB/s FP64/FP32; 64-cell natural order 5.3-5.7);
+//   D3Q19 with >= 2^24 cells: 128-cell blocks, one row range per XCD
+//     (384^3: 5.5 / 5.9 TB/s FP64 / FP32, against 5.0 / 5.4 in natural order);
+//   smaller D3Q19 grids: 64-cell blocks, natural order for double storage,
+//     8-row interleave for float and half (128^3: 5.6 / 5.8 / 5.9 TB/s).
+LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want) {
+    LaunchCfg c = want;
+    const double cells = static_cast<double>(nx) * ny * nz;
+    const bool big3d = Q == 19 && cells >= 16777216.0 && nx > 64;
+    if (c.bx == 0) c.bx = ((Q == 9 && nx >= 128) || big3d) ? 128 : 64;
+    if (c.order < 0) {
+        if (Q == 9) c.order = kOrderInterleave8;
+        else if (big3d) c.order = kOrderXcdRange;
+        else c.order = (mode == kF64) ? kOrderNatural : kOrderInterleave8;
+    }
+    return c;
 }
 
 template <int Q, int MODE, bool PULL, bool COLL>
-static hipError_t launch(const void* src, void* dst, const KParams& p, hipStream_t s) {
+static hipError_t launch(const void* src, void* dst, const KParams& p, LaunchCfg c, hipStream_t s) {
     using T = typename Store<MODE>::T;
-    const int bx = step_bx(p.nx, MODE);
-    const dim3 grd((p.nx + bx - 1) / bx, p.ny, p.nz);
-    if (bx == 64)
+    const dim3 grd(static_cast<unsigned>((p.nx + c.bx - 1) / c.bx) * p.ny * p.nz);
+    if (c.bx == 64)
         hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 64>), grd, dim3(64, 4), 0, s, static_cast<const T*>(src),
-                           static_cast<T*>(dst), p);
+                           static_cast<T*>(dst), p, c.order);
     else
         hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 128>), grd, dim3(128, 4), 0, s,
-                           static_cast<const T*>(src), static_cast<T*>(dst), p);
+                           static_cast<const T*>(src), static_cast<T*>(dst), p, c.order);
     return hipGetLastError();
 }
 
 template <int Q, int MODE>
-static hipError_t dispatch_kind(StepKind kind, const void* src, void* dst, const KParams& p, hipStream_t s) {
+static hipError_t dispatch_kind(StepKind kind, const void* src, void* dst, const KParams& p, LaunchCfg c,
+                                hipStream_t s) {
     switch (kind) {
-        case StepKind::Fused: return launch<Q, MODE, true, true>(src, dst, p, s);
-        case StepKind::CollideOnly: return launch<Q, MODE, false, true>(src, dst, p, s);
-        case StepKind::StreamOnly: return launch<Q, MODE, true, false>(src, dst, p, s);
+        case StepKind::Fused: return launch<Q, MODE, true, true>(src, dst, p, c, s);
+        case StepKind::CollideOnly: return launch<Q, MODE, false, true>(src, dst, p, c, s);
+        case StepKind::StreamOnly: return launch<Q, MODE, true, false>(src, dst, p, c, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_step(StepKind kind, int Q, int mode, const void* src, void* dst, const KParams& p,
-                       hipStream_t s) {
+                       LaunchCfg want, hipStream_t s) {
+    const LaunchCfg c = step_launch(p.nx, p.ny, p.nz, Q, mode, want);
     if (Q == 9) {
-        if (mode == kF64) return dispatch_kind<9, kF64>(kind, src, dst, p, s);
-        if (mode == kF32) return dispatch_kind<9, kF32>(kind, src, dst, p, s);
-        return dispatch_kind<9, kF16Dev>(kind, src, dst, p, s);
+        if (mode == kF64) return dispatch_kind<9, kF64>(kind, src, dst, p, c, s);
+        if (mode == kF32) return dispatch_kind<9, kF32>(kind, src, dst, p, c, s);
+        return dispatch_kind<9, kF16Dev>(kind, src, dst, p, c, s);
     }
-    if (mode == kF64) return dispatch_kind<19, kF64>(kind, src, dst, p, s);
-    if (mode == kF32) return dispatch_kind<19, kF32>(kind, src, dst, p, s);
-    return dispatch_kind<19, kF16Dev>(kind, src, dst, p, s);
+    if (mode == kF64) return dispatch_kind<19, kF64>(kind, src, dst, p, c, s);
+    if (mode == kF32) return dispatch_kind<19, kF32>(kind, src, dst, p, c, s);
+    return dispatch_kind<19, kF16Dev>(kind, src, dst, p, c, s);
 }
 
 }  // namespace mlbm

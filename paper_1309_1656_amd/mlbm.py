@@ -14,6 +14,7 @@ import numpy as np
 MLBM_D2Q9, MLBM_D3Q19 = 9, 19
 MLBM_STORE_F64, MLBM_STORE_F32, MLBM_STORE_F16DEV = 0, 1, 2
 MLBM_EQ_DIRECT, MLBM_EQ_EIGEN = 0, 1
+MLBM_ORDER_AUTO, MLBM_ORDER_NATURAL, MLBM_ORDER_XCD_RANGE, MLBM_ORDER_INTERLEAVE8 = -1, 0, 1, 2
 MLBM_OK, MLBM_EINVAL, MLBM_EDOMAIN, MLBM_EHIP, MLBM_ENOMEM, MLBM_ENONFINITE, MLBM_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmlbm.so")
@@ -21,7 +22,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmlbm.so"
 EXPORTS = (
     "mlbm_create", "mlbm_destroy", "mlbm_get_info", "mlbm_field_bytes", "mlbm_set_tau", "mlbm_set_eq_mode",
     "mlbm_init_equilibrium", "mlbm_step", "mlbm_collide", "mlbm_stream", "mlbm_moments", "mlbm_spin_loss",
-    "mlbm_adjoint_step", "mlbm_set_f16_reference", "mlbm_last_error",
+    "mlbm_adjoint_step", "mlbm_set_f16_reference", "mlbm_set_launch", "mlbm_last_error",
 )
 
 
@@ -40,6 +41,7 @@ class Info(ctypes.Structure):
         ("w", ctypes.c_double * 19), ("c", (ctypes.c_int * 3) * 19),
         ("a1_0", ctypes.c_double), ("a1_b", ctypes.c_double), ("a2_0", ctypes.c_double),
         ("a2_b", ctypes.c_double), ("a3", ctypes.c_double), ("a4", ctypes.c_double), ("a5", ctypes.c_double),
+        ("launch_block_x", ctypes.c_int), ("launch_order", ctypes.c_int),
         ("f16_scale", ctypes.c_double), ("f16_ref", (ctypes.c_double * 19) * 4),
     ]
 
@@ -71,6 +73,7 @@ def load_library(path=LIB_PATH):
         "mlbm_spin_loss": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_adjoint_step": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_set_f16_reference": ([vp, dp, ctypes.c_double], ctypes.c_int),
+        "mlbm_set_launch": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "mlbm_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -283,6 +286,11 @@ def mlbm_adjoint_step(h, W_n, lam_next, lam_n, dL_domega=None, stream=None):
     _check(load_library().mlbm_adjoint_step(
         h.ptr, _field_ptr(h, W_n, "W_n"), _field_ptr(h, lam_next, "lam_next"), _field_ptr(h, lam_n, "lam_n"),
         _dev_ptr(dL_domega, torch.float64, 1, "dL_domega"), _stream_ptr(stream)))
+
+
+def mlbm_set_launch(h, block_x=0, order=MLBM_ORDER_AUTO):
+    _check(load_library().mlbm_set_launch(h.ptr, int(block_x), int(order)))
+    mlbm_get_info(h)
 
 
 def mlbm_set_f16_reference(h, ref, scale):

@@ -104,3 +104,17 @@ def test_host_side_validation():
     assert np.array_equal(h16.info["f16_ref"].ravel(), ref)
     with pytest.raises(mlbm.MlbmError):
         mlbm.mlbm_set_f16_reference(h16, ref, -1.0)
+
+
+def test_set_launch_validation_and_info():
+    h = mlbm.mlbm_create(19, (128, 128, 128), 0.8, 1.0, mlbm.MLBM_STORE_F64)
+    assert h.info["launch_block_x"] in (64, 128)
+    assert h.info["launch_order"] in (0, 1, 2)
+    mlbm.mlbm_set_launch(h, 128, mlbm.MLBM_ORDER_XCD_RANGE)
+    assert h.info["launch_block_x"] == 128 and h.info["launch_order"] == mlbm.MLBM_ORDER_XCD_RANGE
+    for bad in [(32, 0), (256, 0), (64, 3), (64, -2)]:
+        with pytest.raises(mlbm.MlbmError) as e:
+            mlbm.mlbm_set_launch(h, *bad)
+        assert e.value.code == mlbm.MLBM_EINVAL
+    mlbm.mlbm_set_launch(h, 0, mlbm.MLBM_ORDER_AUTO)
+    assert h.info["launch_block_x"] in (64, 128)
