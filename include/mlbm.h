@@ -277,6 +277,24 @@ int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next,
 int mlbm_set_launch(mlbm_handle h, int block_x, int order);
 
 /*
+ * mlbm_adjoint_segment -- the adjoint of nsteps >= 0 consecutive steps in one
+ * call, for checkpointed reverse mode.  W is the segment's first
+ * pre-collision state (its checkpoint; read only).  The nsteps - 1
+ * intermediate states are recomputed into `states`, caller-owned device
+ * memory for nsteps - 1 fields laid out one after the other (may be NULL if
+ * nsteps <= 1), in post-collision form (one fused pass each).  Then the
+ * adjoint steps run from the last to the first, gathering each pre-collision
+ * state from the previous post-collision one:
+ *   lam      on entry dL/da of the state after the segment, on exit dL/da of W;
+ *   lam_tmp  workspace field (clobbered);
+ *   dL_domega device double, accumulated (+=) as in mlbm_adjoint_step.
+ * Same derivative and restrictions as mlbm_adjoint_step; lam, lam_tmp and W
+ * must be distinct.
+ */
+int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps, void* lam,
+                         void* lam_tmp, double* dL_domega, void* stream);
+
+/*
  * mlbm_set_f16_reference -- restore the MLBM_STORE_F16DEV reference R (4*Q
  * doubles, [k][i], host) and scale S > 0 saved from mlbm_get_info, so that a
  * saved F16DEV field can be resumed on a new handle.

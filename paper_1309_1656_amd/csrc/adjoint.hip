@@ -14,6 +14,10 @@
 // One thread per cell; fields are read in the storage type and all
 // arithmetic is in double.  The trace channel is handled first and last so
 // that each Bloch channel k = 1..3 is loaded, used and written in turn.
+//
+// W_n can be read as stored (WPULL = false) or gathered from the previous
+// post-collision state S_{n-1}, W_n,i(x) = S_{n-1},i(x - c_i) (WPULL = true),
+// so that a recomputed segment needs one fused pass per state.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -26,7 +30,7 @@ __device__ __forceinline__ void push_coords(int x, int n, int stride, int out[3]
     out[2] = ((x + 1 == n) ? 0 : x + 1) * stride;
 }
 
-template <int Q, int MODE>
+template <int Q, int MODE, bool WPULL>
 __global__ void __launch_bounds__(256)
 k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<MODE>::T* __restrict__ ln1,
           typename Store<MODE>::T* __restrict__ ln, const KParams p, double* __restrict__ partials) {
@@ -46,17 +50,23 @@ k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<M
         push_coords(x, nx, 1, xp);
         push_coords(y, ny, 1, yp);
         if constexpr (D == 3) push_coords(z, nz, 1, zp);
-        size_t srow[Q];
-        int sx[Q];
+        size_t srow[Q], wrow[Q];
+        int sx[Q], wx[Q];
+        int xm[3], ym[3], zm[3] = {z, z, z};
+        pull_coords(x, nx, 1, xm);
+        pull_coords(y, ny, 1, ym);
+        if constexpr (D == 3) pull_coords(z, nz, 1, zm);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             srow[i] = static_cast<size_t>(zp[Lat<Q>::c(i, 2) + 1]) * ny + yp[Lat<Q>::c(i, 1) + 1];
             sx[i] = xp[Lat<Q>::c(i, 0) + 1];
+            wrow[i] = WPULL ? static_cast<size_t>(zm[Lat<Q>::c(i, 2) + 1]) * ny + ym[Lat<Q>::c(i, 1) + 1] : row;
+            wx[i] = WPULL ? xm[Lat<Q>::c(i, 0) + 1] : x;
         }
         // trace channel of W_n: moments and the polynomial factor
         double a0[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) a0[i] = static_cast<double>(Wn[fidx(Q, nx, row, 0, i, x)]);
+        for (int i = 0; i < Q; ++i) a0[i] = static_cast<double>(Wn[fidx(Q, nx, wrow[i], 0, i, wx[i])]);
         double Tr = 0.0, J[3] = {0.0, 0.0, 0.0}, K = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -101,7 +111,7 @@ k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<M
             double rk = 0.0;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                ak[i] = static_cast<double>(Wn[fidx(Q, nx, row, k, i, x)]);
+                ak[i] = static_cast<double>(Wn[fidx(Q, nx, wrow[i], k, i, wx[i])]);
                 rk += ak[i];
             }
             double hk = 0.0;
@@ -167,22 +177,26 @@ int adjoint_blocks(int nx, int ny, int nz) {
 }
 
 template <int Q, int MODE>
-static hipError_t adj_q(const void* Wn, const void* l1, void* l0, const KParams& p, double* partials,
+static hipError_t adj_q(bool wpull, const void* Wn, const void* l1, void* l0, const KParams& p, double* partials,
                         hipStream_t s) {
     using T = typename Store<MODE>::T;
     dim3 blk = adj_block(p.nx);
     dim3 grd((p.nx + blk.x - 1) / blk.x, (p.ny + blk.y - 1) / blk.y, p.nz);
-    hipLaunchKernelGGL((k_adjoint<Q, MODE>), grd, blk, 0, s, static_cast<const T*>(Wn), static_cast<const T*>(l1),
-                       static_cast<T*>(l0), p, partials);
+    if (wpull)
+        hipLaunchKernelGGL((k_adjoint<Q, MODE, true>), grd, blk, 0, s, static_cast<const T*>(Wn),
+                           static_cast<const T*>(l1), static_cast<T*>(l0), p, partials);
+    else
+        hipLaunchKernelGGL((k_adjoint<Q, MODE, false>), grd, blk, 0, s, static_cast<const T*>(Wn),
+                           static_cast<const T*>(l1), static_cast<T*>(l0), p, partials);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(int Q, int mode, const void* Wn, const void* lam_next, void* lam_n,
+hipError_t launch_adjoint(int Q, int mode, bool wpull, const void* Wn, const void* lam_next, void* lam_n,
                           const KParams& p, double* partials, hipStream_t s) {
-    if (Q == 9) return mode == kF64 ? adj_q<9, kF64>(Wn, lam_next, lam_n, p, partials, s)
-                                    : adj_q<9, kF32>(Wn, lam_next, lam_n, p, partials, s);
-    return mode == kF64 ? adj_q<19, kF64>(Wn, lam_next, lam_n, p, partials, s)
-                        : adj_q<19, kF32>(Wn, lam_next, lam_n, p, partials, s);
+    if (Q == 9) return mode == kF64 ? adj_q<9, kF64>(wpull, Wn, lam_next, lam_n, p, partials, s)
+                                    : adj_q<9, kF32>(wpull, Wn, lam_next, lam_n, p, partials, s);
+    return mode == kF64 ? adj_q<19, kF64>(wpull, Wn, lam_next, lam_n, p, partials, s)
+                        : adj_q<19, kF32>(wpull, Wn, lam_next, lam_n, p, partials, s);
 }
 
 }  // namespace mlbm

@@ -436,8 +436,44 @@ int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next, void
     if (int e = ensure_scratch(h, std::max<size_t>(static_cast<size_t>(nb), static_cast<size_t>(kRedBlocks) * kRedSlots)))
         return e;
     hipStream_t s = as_stream(stream);
-    HIP_TRY(launch_adjoint(h->Q, h->storage, W_n, lam_next, lam_n, h->kp, h->d_partials, s));
+    HIP_TRY(launch_adjoint(h->Q, h->storage, false, W_n, lam_next, lam_n, h->kp, h->d_partials, s));
     if (dL_domega) HIP_TRY(launch_finalize(h->d_partials, nb, 1, 0u, nullptr, dL_domega, 1.0, s));
+    return ok();
+}
+
+int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps, void* lam, void* lam_tmp,
+                         double* dL_domega, void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!W || !lam || !lam_tmp || (nsteps > 1 && !states)) return fail(MLBM_EINVAL, "null field");
+    if (nsteps < 0) return fail(MLBM_EINVAL, "nsteps must be >= 0");
+    if (h->storage == MLBM_STORE_F16DEV) return fail(MLBM_EINVAL, "the adjoint needs F64 or F32 storage");
+    if (h->eq_mode != MLBM_EQ_DIRECT) return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode");
+    if (lam == lam_tmp || lam == W || lam_tmp == W) return fail(MLBM_EINVAL, "lam, lam_tmp and W must be distinct");
+    if (nsteps == 0) return ok();
+    const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));
+    if (int e = ensure_scratch(h, std::max<size_t>(static_cast<size_t>(nb), static_cast<size_t>(kRedBlocks) * kRedSlots)))
+        return e;
+    hipStream_t s = as_stream(stream);
+    size_t fb = 0;
+    mlbm_field_bytes(h, &fb);
+    char* st = static_cast<char*>(states);
+    // forward recomputation: states[j] = post-collision state of step j (j = 0 .. nsteps - 2)
+    if (nsteps > 1) HIP_TRY(launch_step(StepKind::CollideOnly, h->Q, h->storage, W, st, h->kp, h->launch, s));
+    for (int j = 1; j < nsteps - 1; ++j)
+        HIP_TRY(launch_step(StepKind::Fused, h->Q, h->storage, st + (j - 1) * fb, st + j * fb, h->kp, h->launch, s));
+    // reverse sweep: step j reads W_j, gathered from states[j - 1] for j >= 1
+    void* in = lam;
+    void* out = lam_tmp;
+    for (int j = nsteps - 1; j >= 0; --j) {
+        const bool pulled = j > 0;
+        const void* wsrc = pulled ? static_cast<const void*>(st + (j - 1) * fb) : W;
+        HIP_TRY(launch_adjoint(h->Q, h->storage, pulled, wsrc, in, out, h->kp, h->d_partials, s));
+        if (dL_domega) HIP_TRY(launch_finalize(h->d_partials, nb, 1, 0u, nullptr, dL_domega, 1.0, s));
+        void* t = in;
+        in = out;
+        out = t;
+    }
+    if (in != lam) HIP_TRY(hipMemcpyAsync(lam, in, fb, hipMemcpyDeviceToDevice, s));
     return ok();
 }
 

@@ -44,8 +44,9 @@ hipError_t launch_spin_loss(int Q, int mode, const void* W, const double* r_targ
                             const KParams& p, double* partials, hipStream_t s);
 
 // Adjoint of one step: one partial of dL/domega per block
-// (adjoint_blocks(nx, ny, nz) values, stride 1).
-hipError_t launch_adjoint(int Q, int mode, const void* Wn, const void* lam_next, void* lam_n,
+// (adjoint_blocks(nx, ny, nz) values, stride 1).  With wpull, Wn is the
+// previous post-collision state and W_n is gathered from it by a pull.
+hipError_t launch_adjoint(int Q, int mode, bool wpull, const void* Wn, const void* lam_next, void* lam_n,
                           const KParams& p, double* partials, hipStream_t s);
 
 // Initial Fermi-Dirac state.  phase 0: only reduce global sums (slots 0..3

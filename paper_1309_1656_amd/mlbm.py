@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmlbm.so"
 EXPORTS = (
     "mlbm_create", "mlbm_destroy", "mlbm_get_info", "mlbm_field_bytes", "mlbm_set_tau", "mlbm_set_eq_mode",
     "mlbm_init_equilibrium", "mlbm_step", "mlbm_collide", "mlbm_stream", "mlbm_moments", "mlbm_spin_loss",
-    "mlbm_adjoint_step", "mlbm_set_f16_reference", "mlbm_set_launch", "mlbm_last_error",
+    "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_set_f16_reference", "mlbm_set_launch",
+    "mlbm_last_error",
 )
 
 
@@ -72,6 +73,7 @@ def load_library(path=LIB_PATH):
         "mlbm_moments": ([vp, vp, vp, vp, vp, dp, i64p, vp], ctypes.c_int),
         "mlbm_spin_loss": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_adjoint_step": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "mlbm_adjoint_segment": ([vp, vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_set_f16_reference": ([vp, dp, ctypes.c_double], ctypes.c_int),
         "mlbm_set_launch": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "mlbm_last_error": ([], ctypes.c_char_p),
@@ -291,6 +293,19 @@ def mlbm_adjoint_step(h, W_n, lam_next, lam_n, dL_domega=None, stream=None):
 def mlbm_set_launch(h, block_x=0, order=MLBM_ORDER_AUTO):
     _check(load_library().mlbm_set_launch(h.ptr, int(block_x), int(order)))
     mlbm_get_info(h)
+
+
+def mlbm_adjoint_segment(h, W, states, nsteps, lam, lam_tmp, dL_domega=None, stream=None):
+    """states: device tensor holding at least nsteps - 1 fields (e.g. shape [n - 1, *field_shape]) or None."""
+    import torch
+    if nsteps > 1:
+        need = (nsteps - 1) * 4 * h.Q * h.info["ncell"]
+        if states is None or states.dtype != h.field_dtype or states.numel() < need or not states.is_contiguous():
+            raise MlbmError(MLBM_EINVAL, f"states must hold {nsteps - 1} contiguous fields")
+    _check(load_library().mlbm_adjoint_segment(
+        h.ptr, _field_ptr(h, W, "W"), None if states is None else _dev_ptr(states, name="states"), int(nsteps),
+        _field_ptr(h, lam, "lam"), _field_ptr(h, lam_tmp, "lam_tmp"),
+        _dev_ptr(dL_domega, torch.float64, 1, "dL_domega"), _stream_ptr(stream)))
 
 
 def mlbm_set_f16_reference(h, ref, scale):

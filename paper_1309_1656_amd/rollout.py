@@ -3,10 +3,10 @@ its hand-written adjoint, with checkpoints every K steps.
 
 Loss: L = (1/N) sum_x |r(x, n) - r_target(x)|^2, r the Bloch vector of
 rho(x) = sum_i W_i(x) after n steps (mlbm_spin_loss).  Backward: for each
-K-step segment, newest first, the segment's states are recomputed from its
-checkpoint with the forward step and the adjoint steps run in reverse
-(mlbm_adjoint_step), accumulating dL/domega on the device; dL/dtau =
--dL/domega / tau^2.  Memory: one checkpoint per segment plus K states.
+K-step segment, newest first, one mlbm_adjoint_segment call recomputes the
+segment's states from its checkpoint (one fused pass each) and runs the
+adjoint steps in reverse, accumulating dL/domega on the device; dL/dtau =
+-dL/domega / tau^2.  Memory: one checkpoint per segment plus K - 1 states.
 """
 import torch
 
@@ -50,19 +50,12 @@ class MLBMRollout(torch.autograd.Function):
         mlbm.mlbm_set_tau(h, ctx.tau)
         lam = torch.empty_like(ctx.final)
         mlbm.mlbm_spin_loss(h, ctx.final, ctx.r_target, lam=lam)
-        lam_new = torch.empty_like(lam)
-        scratch = torch.empty_like(lam)
+        lam_tmp = torch.empty_like(lam)
+        states = torch.empty((K - 1,) + tuple(lam.shape), dtype=lam.dtype, device=lam.device) if K > 1 else None
         domega = torch.zeros(1, dtype=torch.float64, device=lam.device)
         for s in range(len(ctx.ckpts) - 1, -1, -1):
             n = min(K, nsteps - s * K)
-            states = [ctx.ckpts[s]]
-            W = ctx.ckpts[s].clone()
-            for _ in range(n - 1):
-                mlbm.mlbm_step(h, W, scratch, 1)
-                states.append(W.clone())
-            for j in range(n - 1, -1, -1):
-                mlbm.mlbm_adjoint_step(h, states[j], lam, lam_new, domega)
-                lam, lam_new = lam_new, lam
+            mlbm.mlbm_adjoint_segment(h, ctx.ckpts[s], states, n, lam, lam_tmp, domega)
         grad_W0 = lam * gL.to(lam.dtype) if ctx.needs_input_grad[0] else None
         grad_tau = None
         if ctx.needs_input_grad[1]:

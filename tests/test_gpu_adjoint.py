@@ -117,3 +117,32 @@ def test_spin_loss_matches_oracle():
     got = to_pauli_np(h, lam)
     assert np.all(got[0] == 0)
     assert np.max(np.abs(got[1:] - ref[1:])) <= 1e-13 * np.abs(ref[1:]).max()
+
+
+@pytest.mark.parametrize("shape,n", [((37, 70), 7), ((13, 9, 11), 4), ((16, 16), 1)])
+def test_adjoint_segment_equals_stepwise(shape, n):
+    """One mlbm_adjoint_segment call == n recomputed states + n mlbm_adjoint_step calls."""
+    f = fields(shape, 31)
+    h = make_handle(shape, tau=0.7)
+    W0 = gpu_init(h, f)
+    rng = np.random.default_rng(6)
+    lamN = from_pauli(h, rng.standard_normal((4, h.Q) + tuple(shape)))
+    # step by step
+    states = [W0.clone()]
+    W = W0.clone()
+    for _ in range(n - 1):
+        mlbm.mlbm_step(h, W, h.empty_field(), 1)
+        states.append(W.clone())
+    lam = lamN.clone()
+    out = h.empty_field()
+    dom_a = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for j in range(n - 1, -1, -1):
+        mlbm.mlbm_adjoint_step(h, states[j], lam, out, dom_a)
+        lam, out = out, lam
+    # one call
+    lam_b = lamN.clone()
+    buf = torch.empty((max(n - 1, 1),) + tuple(W0.shape), dtype=W0.dtype, device="cuda") if n > 1 else None
+    dom_b = torch.zeros(1, dtype=torch.float64, device="cuda")
+    mlbm.mlbm_adjoint_segment(h, W0, buf, n, lam_b, h.empty_field(), dom_b)
+    assert torch.equal(lam, lam_b)
+    assert dom_a.item() == dom_b.item()
