@@ -74,14 +74,25 @@ def time_region(fn, reps=1):
     return a.elapsed_time(b) / reps
 
 
-def measure_step(shape, seed, tau, storage, steps, warmup, f):
-    """MLUPS of mlbm_step(steps) and the fused kernel's average duration."""
+def measure_step(shape, seed, tau, storage, steps, warmup, f, field=None):
+    """MLUPS of mlbm_step(steps) and the fused kernel's average duration.
+
+    field: None, "uniform" (one mu B for the grid) or "map" (mu B per cell,
+    read by every step: 24 more bytes per cell)."""
     import torch
     from paper_1309_1656_amd import mlbm
     Q = 9 if len(shape) == 2 else 19
     h = mlbm.mlbm_create(Q, dims_of(shape), tau, 1.0, storage)
     W = h.empty_field()
     mlbm.mlbm_init_equilibrium(h, W, *device_inputs(h, f))
+    extra_bytes = 0
+    if field == "uniform":
+        mlbm.mlbm_set_magnetic_field(h, [0.01, -0.02, 0.03])
+    elif field == "map":
+        rng = np.random.default_rng(seed + 7)
+        bmap = torch.from_numpy(rng.normal(0, 0.02, size=(3,) + tuple(shape))).cuda()
+        mlbm.mlbm_set_magnetic_field_map(h, bmap)
+        extra_bytes = 3 * 8
     scratch = h.empty_field()
     g0, _ = mlbm.mlbm_moments(h, W)
     if warmup:
@@ -93,7 +104,7 @@ def measure_step(shape, seed, tau, storage, steps, warmup, f):
     g1, nneg = mlbm.mlbm_moments(h, W)
     N = int(np.prod(shape))
     fused_ms = (t_all - t_pair) / max(steps - 1, 1)
-    bytes_per_cell = 2 * 4 * Q * {0: 8, 1: 4, 2: 2}[storage]
+    bytes_per_cell = 2 * 4 * Q * {0: 8, 1: 4, 2: 2}[storage] + extra_bytes
     achieved = bytes_per_cell * N / (fused_ms * 1e-3) / 1e9
     drift = float(np.max(np.abs(g1 - g0)) / np.max(np.abs(g0)))
     out = {
@@ -230,6 +241,13 @@ def main():
             log(f"{name} step")
             extras[name] = measure_step(shape, wl["seed"], tau, st, args.steps, args.warmup, f)
             log(f"  {extras[name]['mlups']:.0f} MLUPS, {extras[name]['fused_kernel_GBps']:.0f} GB/s")
+        extras["magnetic_f64"] = {}
+        for kind in ("uniform", "map"):
+            log(f"FP64 step with a {kind} magnetic field")
+            extras["magnetic_f64"][kind] = measure_step(shape, wl["seed"], tau, mlbm.MLBM_STORE_F64, args.steps,
+                                                        args.warmup, f, field=kind)
+            log(f"  {extras['magnetic_f64'][kind]['mlups']:.0f} MLUPS, "
+                f"{extras['magnetic_f64'][kind]['fused_kernel_GBps']:.0f} GB/s")
         log("forward + adjoint rollout")
         extras["adjoint"] = measure_adjoint(args.warmup)
         log(f"  ratio {extras['adjoint']['ratio_to_f64_forward']:.2f}")

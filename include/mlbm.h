@@ -264,6 +264,28 @@ int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next,
                       void* lam_n, double* dL_domega, void* stream);
 
 /*
+ * mlbm_set_magnetic_field -- uniform external magnetic field (Sec. 5,
+ * Eq. sigmaB_comm): the commutator -i [mu sigma.B, W] joins the collision.
+ * mu_b[3] (host) is the product mu B of magnetic moment and field; NULL or
+ * zero switches the field off.  Reading: over each time step the commutator
+ * is integrated exactly, W_i -> U W_i U* with U = exp(-i Delta t sigma.(mu B)),
+ * i.e. every Bloch vector turns by 2 Delta t |mu B| about B; it commutes with
+ * the BGK collision of a cell, so the order of the two does not matter.
+ * Traces (density, momentum, energy) are untouched; tr(rho sigma) precesses.
+ * Not combinable with MLBM_EQ_EIGEN or the adjoint (MLBM_EINVAL).
+ */
+int mlbm_set_magnetic_field(mlbm_handle h, const double mu_b[3]);
+
+/*
+ * mlbm_set_magnetic_field_map -- spatially varying field: mu_b is caller-owned
+ * device memory [3][N] (double, plain cell order) holding mu B per cell,
+ * read by every later step (update it between steps for a time-dependent
+ * field); NULL switches the field off.  Same reading and restrictions as
+ * mlbm_set_magnetic_field.
+ */
+int mlbm_set_magnetic_field_map(mlbm_handle h, const double* mu_b);
+
+/*
  * mlbm_set_launch -- launch shape of the step kernels (performance only; the
  * results are identical).  Each workgroup covers block_x consecutive cells
  * of one x-row with four waves per 64 cells, one per Pauli component

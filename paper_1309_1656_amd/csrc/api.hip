@@ -206,6 +206,9 @@ int mlbm_create(mlbm_handle* out, int lattice, const int64_t dims[3], double tau
     for (int k = 0; k < 4; ++k)
         for (int i = 0; i < 19; ++i) p.ref[k][i] = 0.0f;
     for (int i = 0; i < 19; ++i) p.sc[i] = p.inv_sc[i] = 1.0f;
+    p.field_mode = kFieldNone;
+    p.bmap = nullptr;
+    for (int j = 0; j < 9; ++j) p.rot[j] = (j % 4 == 0) ? 1.0 : 0.0;
     gauss_legendre(kGL, h->fp.gl_x, h->fp.gl_w);
     *out = h;
     return ok();
@@ -275,7 +278,43 @@ int mlbm_set_eq_mode(mlbm_handle h, int mode) {
     if (mode != MLBM_EQ_DIRECT && mode != MLBM_EQ_EIGEN) return fail(MLBM_EINVAL, "bad equilibrium mode");
     if (mode == MLBM_EQ_EIGEN && h->storage != MLBM_STORE_F64)
         return fail(MLBM_EINVAL, "the eigen-channel mode needs double storage");
+    if (mode == MLBM_EQ_EIGEN && h->kp.field_mode != kFieldNone)
+        return fail(MLBM_EINVAL, "the eigen-channel mode does not take a magnetic field");
     h->eq_mode = mode;
+    return ok();
+}
+
+int mlbm_set_magnetic_field(mlbm_handle h, const double mu_b[3]) {
+    if (int e = check_handle(h)) return e;
+    const bool off = !mu_b || (mu_b[0] == 0.0 && mu_b[1] == 0.0 && mu_b[2] == 0.0);
+    if (!off) {
+        if (!(std::isfinite(mu_b[0]) && std::isfinite(mu_b[1]) && std::isfinite(mu_b[2])))
+            return fail(MLBM_EINVAL, "non-finite magnetic field");
+        if (h->eq_mode != MLBM_EQ_DIRECT) return fail(MLBM_EINVAL, "the eigen-channel mode does not take a magnetic field");
+    }
+    KParams& p = h->kp;
+    p.bmap = nullptr;
+    if (off) {
+        p.field_mode = kFieldNone;
+        for (int j = 0; j < 9; ++j) p.rot[j] = (j % 4 == 0) ? 1.0 : 0.0;
+        return ok();
+    }
+    // rotation by theta = 2 dt |mu B| about n = B / |B| (Rodrigues), dt = 1
+    const double bb = std::sqrt(mu_b[0] * mu_b[0] + mu_b[1] * mu_b[1] + mu_b[2] * mu_b[2]);
+    const double n[3] = {mu_b[0] / bb, mu_b[1] / bb, mu_b[2] / bb};
+    const double cs = std::cos(2.0 * bb), sn = std::sin(2.0 * bb);
+    const double cx[3][3] = {{0.0, -n[2], n[1]}, {n[2], 0.0, -n[0]}, {-n[1], n[0], 0.0}};
+    for (int k = 0; k < 3; ++k)
+        for (int l = 0; l < 3; ++l) p.rot[k * 3 + l] = (k == l ? cs : 0.0) + sn * cx[k][l] + (1.0 - cs) * n[k] * n[l];
+    p.field_mode = kFieldUniform;
+    return ok();
+}
+
+int mlbm_set_magnetic_field_map(mlbm_handle h, const double* mu_b) {
+    if (int e = check_handle(h)) return e;
+    if (mu_b && h->eq_mode != MLBM_EQ_DIRECT) return fail(MLBM_EINVAL, "the eigen-channel mode does not take a magnetic field");
+    h->kp.bmap = mu_b;
+    h->kp.field_mode = mu_b ? kFieldMap : kFieldNone;
     return ok();
 }
 
@@ -431,6 +470,7 @@ int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next, void
     if (!W_n || !lam_next || !lam_n) return fail(MLBM_EINVAL, "null field");
     if (h->storage == MLBM_STORE_F16DEV) return fail(MLBM_EINVAL, "the adjoint needs F64 or F32 storage");
     if (h->eq_mode != MLBM_EQ_DIRECT) return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode");
+    if (h->kp.field_mode != kFieldNone) return fail(MLBM_EINVAL, "the adjoint does not take a magnetic field");
     if (lam_n == W_n || lam_n == lam_next) return fail(MLBM_EINVAL, "lam_n must not alias the inputs");
     const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));
     if (int e = ensure_scratch(h, std::max<size_t>(static_cast<size_t>(nb), static_cast<size_t>(kRedBlocks) * kRedSlots)))
@@ -448,6 +488,7 @@ int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps,
     if (nsteps < 0) return fail(MLBM_EINVAL, "nsteps must be >= 0");
     if (h->storage == MLBM_STORE_F16DEV) return fail(MLBM_EINVAL, "the adjoint needs F64 or F32 storage");
     if (h->eq_mode != MLBM_EQ_DIRECT) return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode");
+    if (h->kp.field_mode != kFieldNone) return fail(MLBM_EINVAL, "the adjoint does not take a magnetic field");
     if (lam == lam_tmp || lam == W || lam_tmp == W) return fail(MLBM_EINVAL, "lam, lam_tmp and W must be distinct");
     if (nsteps == 0) return ok();
     const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));

@@ -13,6 +13,7 @@
 namespace mlbm {
 
 enum StoreMode { kF64 = 0, kF32 = 1, kF16Dev = 2 };
+enum FieldMode { kFieldNone = 0, kFieldUniform = 1, kFieldMap = 2 };
 
 template <int Q> struct Lat;
 
@@ -62,6 +63,11 @@ struct KParams {
     float ref[4][19];
     float sc[19];
     float inv_sc[19];
+    // magnetic field (Sec. 5): uniform rotation of the Bloch vectors, or a
+    // per-cell map mu B [3][N] (device) from which each cell's rotation follows
+    int field_mode;
+    double rot[9];
+    const double* bmap;
 };
 
 template <int MODE> struct Store;

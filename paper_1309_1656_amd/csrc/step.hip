@@ -103,7 +103,29 @@ __device__ __forceinline__ void block_order(int order, int nx, int ny, int bx, i
     z = static_cast<int>(row / static_cast<unsigned>(ny));
 }
 
-template <int Q, int MODE, bool PULL, bool COLL, int BX>
+// Row k of the rotation of the Bloch vector produced by the magnetic-field
+// commutator -i [mu sigma.B, W] over one time step (Sec. 5, Eq. sigmaB_comm):
+// W -> U W U*, U = exp(-i Delta t sigma.(mu B)), turns every Bloch vector by
+// theta = 2 Delta t |mu B| about the unit axis n of B (Rodrigues):
+//   R = cos(theta) I + sin(theta) [n]x + (1 - cos(theta)) n n^T.
+__device__ __forceinline__ void rotation_row(const double b[3], int k, double r[3]) {
+    const double bb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    if (bb == 0.0) {
+        r[0] = (k == 0) ? 1.0 : 0.0;
+        r[1] = (k == 1) ? 1.0 : 0.0;
+        r[2] = (k == 2) ? 1.0 : 0.0;
+        return;
+    }
+    double sn, cs;
+    sincos(2.0 * bb, &sn, &cs);
+    const double n[3] = {b[0] / bb, b[1] / bb, b[2] / bb};
+    // [n]x row k: (0, -n2, n1), (n2, 0, -n0), (-n1, n0, 0)
+    const double cx[3][3] = {{0.0, -n[2], n[1]}, {n[2], 0.0, -n[0]}, {-n[1], n[0], 0.0}};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) r[l] = ((k == l) ? cs : 0.0) + sn * cx[k][l] + (1.0 - cs) * n[k] * n[l];
+}
+
+template <int Q, int MODE, bool PULL, bool COLL, int BX, int FIELD>
 __global__ void __launch_bounds__(BX * 4)
 k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T* __restrict__ dst,
        const KParams p, const int order) {
@@ -151,7 +173,10 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
         }
         return;
     } else {
-        __shared__ C qs[Q][BX];
+        // q_i of the trace wave; with a field the same LDS is reused for the
+        // exchange of the three Bloch channels (3 Q BX values)
+        __shared__ C lds[(FIELD != kFieldNone ? 3 : 1) * Q * BX];
+        C (*qs)[BX] = reinterpret_cast<C (*)[BX]>(lds);
         C a[Q];
         double rk = 0.0;
 #pragma unroll
@@ -197,7 +222,6 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
             }
         }
         __syncthreads();
-        if (!active) return;
         // collision (Eq. CollisionStep) of this wave's channel
         const C r = static_cast<C>(rk);
         const C omm = cst<C>(p.one_m_om, p.one_m_omf);
@@ -205,9 +229,37 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
 #pragma unroll
         for (int i = 0; i < Q; ++i) S[i] = omm * a[i] + qs[i][lx] * r;
         if constexpr (MODE == kF32) conserve<Q>(S, a, k);
+        if constexpr (FIELD != kFieldNone) {
+            // magnetic precession of the Bloch components; it commutes with the
+            // BGK collision cell by cell, so applying it afterwards is exact
+            C (*sb)[Q][BX] = reinterpret_cast<C (*)[Q][BX]>(lds);
+            __syncthreads();          // every wave has read qs
+            if (k > 0) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i)
-            __builtin_nontemporal_store(encode<MODE>(S[i], k, i, p), dst + fidx(Q, nx, row, k, i, x));
+                for (int i = 0; i < Q; ++i) sb[k - 1][i][lx] = S[i];
+            }
+            __syncthreads();
+            if (k > 0) {
+                double rr[3];
+                if constexpr (FIELD == kFieldUniform) {
+#pragma unroll
+                    for (int l = 0; l < 3; ++l) rr[l] = p.rot[(k - 1) * 3 + l];
+                } else {
+                    const size_t cell = row * nx + xx;
+                    const size_t N = static_cast<size_t>(p.ncell);
+                    const double b[3] = {p.bmap[cell], p.bmap[N + cell], p.bmap[2 * N + cell]};
+                    rotation_row(b, k - 1, rr);
+                }
+                const C r0 = static_cast<C>(rr[0]), r1 = static_cast<C>(rr[1]), r2 = static_cast<C>(rr[2]);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) S[i] = r0 * sb[0][i][lx] + r1 * sb[1][i][lx] + r2 * sb[2][i][lx];
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                __builtin_nontemporal_store(encode<MODE>(S[i], k, i, p), dst + fidx(Q, nx, row, k, i, x));
+        }
     }
 }
 
@@ -232,26 +284,33 @@ LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want) {
     return c;
 }
 
-template <int Q, int MODE, bool PULL, bool COLL>
+template <int Q, int MODE, bool PULL, bool COLL, int FIELD>
 static hipError_t launch(const void* src, void* dst, const KParams& p, LaunchCfg c, hipStream_t s) {
     using T = typename Store<MODE>::T;
     const dim3 grd(static_cast<unsigned>((p.nx + c.bx - 1) / c.bx) * p.ny * p.nz);
     if (c.bx == 64)
-        hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 64>), grd, dim3(64, 4), 0, s, static_cast<const T*>(src),
-                           static_cast<T*>(dst), p, c.order);
+        hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 64, FIELD>), grd, dim3(64, 4), 0, s,
+                           static_cast<const T*>(src), static_cast<T*>(dst), p, c.order);
     else
-        hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 128>), grd, dim3(128, 4), 0, s,
+        hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 128, FIELD>), grd, dim3(128, 4), 0, s,
                            static_cast<const T*>(src), static_cast<T*>(dst), p, c.order);
     return hipGetLastError();
+}
+
+template <int Q, int MODE, bool PULL>
+static hipError_t launch_coll(const void* src, void* dst, const KParams& p, LaunchCfg c, hipStream_t s) {
+    if (p.field_mode == kFieldUniform) return launch<Q, MODE, PULL, true, kFieldUniform>(src, dst, p, c, s);
+    if (p.field_mode == kFieldMap) return launch<Q, MODE, PULL, true, kFieldMap>(src, dst, p, c, s);
+    return launch<Q, MODE, PULL, true, kFieldNone>(src, dst, p, c, s);
 }
 
 template <int Q, int MODE>
 static hipError_t dispatch_kind(StepKind kind, const void* src, void* dst, const KParams& p, LaunchCfg c,
                                 hipStream_t s) {
     switch (kind) {
-        case StepKind::Fused: return launch<Q, MODE, true, true>(src, dst, p, c, s);
-        case StepKind::CollideOnly: return launch<Q, MODE, false, true>(src, dst, p, c, s);
-        case StepKind::StreamOnly: return launch<Q, MODE, true, false>(src, dst, p, c, s);
+        case StepKind::Fused: return launch_coll<Q, MODE, true>(src, dst, p, c, s);
+        case StepKind::CollideOnly: return launch_coll<Q, MODE, false>(src, dst, p, c, s);
+        case StepKind::StreamOnly: return launch<Q, MODE, true, false, kFieldNone>(src, dst, p, c, s);
     }
     return hipErrorInvalidValue;
 }

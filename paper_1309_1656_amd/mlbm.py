@@ -23,7 +23,7 @@ EXPORTS = (
     "mlbm_create", "mlbm_destroy", "mlbm_get_info", "mlbm_field_bytes", "mlbm_set_tau", "mlbm_set_eq_mode",
     "mlbm_init_equilibrium", "mlbm_step", "mlbm_collide", "mlbm_stream", "mlbm_moments", "mlbm_spin_loss",
     "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_set_f16_reference", "mlbm_set_launch",
-    "mlbm_last_error",
+    "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_last_error",
 )
 
 
@@ -76,6 +76,8 @@ def load_library(path=LIB_PATH):
         "mlbm_adjoint_segment": ([vp, vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_set_f16_reference": ([vp, dp, ctypes.c_double], ctypes.c_int),
         "mlbm_set_launch": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "mlbm_set_magnetic_field": ([vp, dp], ctypes.c_int),
+        "mlbm_set_magnetic_field_map": ([vp, vp], ctypes.c_int),
         "mlbm_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -288,6 +290,23 @@ def mlbm_adjoint_step(h, W_n, lam_next, lam_n, dL_domega=None, stream=None):
     _check(load_library().mlbm_adjoint_step(
         h.ptr, _field_ptr(h, W_n, "W_n"), _field_ptr(h, lam_next, "lam_next"), _field_ptr(h, lam_n, "lam_n"),
         _dev_ptr(dL_domega, torch.float64, 1, "dL_domega"), _stream_ptr(stream)))
+
+
+def mlbm_set_magnetic_field(h, mu_b):
+    """Uniform mu B (three numbers), or None to switch the field off."""
+    arr = None if mu_b is None else (ctypes.c_double * 3)(*[float(v) for v in mu_b])
+    _check(load_library().mlbm_set_magnetic_field(h.ptr, arr))
+
+
+def mlbm_set_magnetic_field_map(h, mu_b):
+    """Per-cell mu B as a float64 device tensor [3, *grid] (kept alive by the caller), or None."""
+    if mu_b is None:
+        _check(load_library().mlbm_set_magnetic_field_map(h.ptr, None))
+        h._field_map = None
+        return
+    ptr = _f64_ptr(h, mu_b, 3, "mu_b")
+    _check(load_library().mlbm_set_magnetic_field_map(h.ptr, ptr))
+    h._field_map = mu_b          # keep the device memory alive while the handle uses it
 
 
 def mlbm_set_launch(h, block_x=0, order=MLBM_ORDER_AUTO):

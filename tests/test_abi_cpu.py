@@ -118,3 +118,30 @@ def test_set_launch_validation_and_info():
         assert e.value.code == mlbm.MLBM_EINVAL
     mlbm.mlbm_set_launch(h, 0, mlbm.MLBM_ORDER_AUTO)
     assert h.info["launch_block_x"] in (64, 128)
+
+
+def test_magnetic_field_validation():
+    lib = mlbm.load_library()
+    h = mlbm.mlbm_create(19, (8, 7, 6), 0.8, 1.0, mlbm.MLBM_STORE_F64)
+    mlbm.mlbm_set_magnetic_field(h, [0.1, 0.0, -0.2])
+    # the field excludes the eigen-channel mode and the adjoint
+    with pytest.raises(mlbm.MlbmError) as e:
+        mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_EIGEN)
+    assert e.value.code == mlbm.MLBM_EINVAL
+    buf = [ctypes.c_void_p(4096 * (j + 1)) for j in range(3)]
+    assert lib.mlbm_adjoint_step(h.ptr, buf[0], buf[1], buf[2], None, None) == mlbm.MLBM_EINVAL
+    assert "magnetic" in mlbm.mlbm_last_error()
+    with pytest.raises(mlbm.MlbmError):
+        mlbm.mlbm_set_magnetic_field(h, [float("nan"), 0.0, 0.0])
+    # switched off (None or zero): both are allowed again
+    mlbm.mlbm_set_magnetic_field(h, [0.0, 0.0, 0.0])
+    mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_EIGEN)
+    with pytest.raises(mlbm.MlbmError) as e:
+        mlbm.mlbm_set_magnetic_field(h, [0.1, 0.2, 0.3])
+    assert e.value.code == mlbm.MLBM_EINVAL
+    assert lib.mlbm_set_magnetic_field_map(h.ptr, ctypes.c_void_p(4096)) == mlbm.MLBM_EINVAL
+    mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_DIRECT)
+    assert lib.mlbm_set_magnetic_field_map(h.ptr, ctypes.c_void_p(4096)) == mlbm.MLBM_OK
+    assert lib.mlbm_adjoint_step(h.ptr, buf[0], buf[1], buf[2], None, None) == mlbm.MLBM_EINVAL
+    mlbm.mlbm_set_magnetic_field(h, None)
+    assert lib.mlbm_set_magnetic_field(None, None) == mlbm.MLBM_EINVAL
