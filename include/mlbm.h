@@ -45,7 +45,8 @@
  *                      of two at or above max |a - R| / w_i over the initial
  *                      field, and s_i = 2^round(log2(w_i S)) (|h| <= sqrt 2
  *                      initially; both scalings are exact).  R and S are fixed
- *                      by mlbm_init_equilibrium and kept in the handle.
+ *                      by mlbm_init_equilibrium (or mlbm_init_chemical) and
+ *                      kept in the handle.
  *                      Encoding rounds to nearest even; arithmetic in float,
  *                      moment sums in double.
  *
@@ -64,8 +65,9 @@
  *
  * Streams.  Every call that takes `stream` (a hipStream_t; NULL means the
  * null stream) enqueues its work asynchronously on that stream and returns.
- * The exceptions synchronise `stream` and say so: mlbm_init_equilibrium
- * (reads back status flags) and mlbm_moments when a host output is requested.
+ * The exceptions synchronise `stream` and say so: mlbm_init_equilibrium and
+ * mlbm_init_chemical (read back status flags) and mlbm_moments when a host
+ * output is requested.
  * A handle must not be used by two host threads at once; calls on one handle
  * on different streams must be ordered by the caller.
  *
@@ -186,6 +188,23 @@ int mlbm_set_eq_mode(mlbm_handle h, int mode);
  */
 int mlbm_init_equilibrium(mlbm_handle h, void* W, const double* rho4,
                           const double* u, const double* T, void* stream);
+
+/*
+ * mlbm_init_chemical -- the same discrete Fermi-Dirac equilibrium, with each
+ * cell named by its chemical potentials as in the Riemann problem of Sec. 4:
+ *   nu   [2][N] double (device): nu_up = beta mu_up and nu_dn = beta mu_dn;
+ *   axis [3][N] double (device) or NULL: the spin axis a of the up channel
+ *        (any nonzero length, normalised per cell); NULL means +z;
+ *   u, T as for mlbm_init_equilibrium.
+ * Per cell n_up/dn = (2 pi / beta)^(d/2) F_{d/2-1}(nu_up/dn) (Eq. nFDstdOmega),
+ * rho = U diag(n_up, n_dn) U* = ((n_up + n_dn) I + (n_up - n_dn) a . sigma)/2,
+ * eps as above (Eq. energyFDstdOmega), W_i = w_i rho P_i(u, eps).
+ * Synchronises `stream`.  Errors: MLBM_EINVAL (null W, nu, u or T),
+ * MLBM_EDOMAIN (some cell has T <= 0, a zero or non-finite axis, nu > 4000 or
+ * a non-finite input), MLBM_EHIP.  F16DEV reference and scale as above.
+ */
+int mlbm_init_chemical(mlbm_handle h, void* W, const double* nu, const double* axis, const double* u,
+                       const double* T, void* stream);
 
 /*
  * mlbm_step -- advance W by nsteps >= 0 time steps (Sec. 3.3).  W holds the

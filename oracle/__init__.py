@@ -21,6 +21,9 @@ Modules
   eigen      the equilibrium built through the eigen-decomposition of rho and
              the Fermi-Dirac parameters (Prop. 1, Eqs. WeqFD, WeqDiscr)
   adjoint    reverse-mode derivative of the step and of the spin loss
+  magnetic   the collision with an external magnetic field (Sec. 5)
+  euler      the exact solution of the Riemann problem of the Euler
+             equations (Eq. Euler), the reference of the Riemann workload
   pauli      conversion between the matrix form and Pauli coefficients
 
 Parity status: every function here is pinned by a CPU test against values the

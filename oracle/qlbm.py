@@ -177,6 +177,34 @@ def init_equilibrium(lat, trrho, r, u, T):
     return equilibrium(lat, density_matrix(trrho, r), u, eps)
 
 
+def init_chemical(lat, nu_up, nu_dn, u, T, axis=None):
+    """Fermi-Dirac equilibrium named by the channels' chemical potentials.
+
+    nu_s = beta mu_s per cell; the up channel is polarised along the unit
+    vector `axis` ([3, *grid], default +z).  The channel densities are
+    Eq. nFDstdOmega, rho = U diag(n_up, n_dn) U* with U turning z onto the axis,
+    and eps is Eq. energyFDstdOmega (the Riemann problem of Sec. 4 starts from
+    such states with u = 0 and beta = 1).
+    """
+    nu_up = np.asarray(nu_up, dtype=np.float64)
+    nu_dn = np.asarray(nu_dn, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    if np.any(~(T > 0)):
+        raise ValueError("T must be positive")
+    beta = 1.0 / T
+    n_up = fermi.channel_density(lat.d, beta, nu_up)
+    n_dn = fermi.channel_density(lat.d, beta, nu_dn)
+    if axis is None:
+        axis = np.zeros((3,) + nu_up.shape)
+        axis[2] = 1.0
+    axis = np.asarray(axis, dtype=np.float64)
+    axis = axis / np.sqrt((axis ** 2).sum(axis=0))
+    # U diag(n_up, n_dn) U* = ((n_up + n_dn) I + (n_up - n_dn) axis . sigma) / 2
+    rho = density_matrix(n_up + n_dn, (n_up - n_dn) * axis)
+    eps = fermi.internal_energy(lat.d, beta, nu_up, nu_dn)
+    return equilibrium(lat, rho, np.asarray(u, dtype=np.float64), eps)
+
+
 def bloch(rho):
     """Bloch vector r_k = tr(rho s_k), k = 1..3 (Sec. 4, interference example)."""
     return pauli_from_matrix(rho)[1:]

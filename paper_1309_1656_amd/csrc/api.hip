@@ -338,16 +338,16 @@ int mlbm_set_f16_reference(mlbm_handle h, const double* ref, double scale) {
     return ok();
 }
 
-int mlbm_init_equilibrium(mlbm_handle h, void* W, const double* rho4, const double* u, const double* T,
-                          void* stream) {
-    if (int e = check_handle(h)) return e;
-    if (!W || !rho4 || !u || !T) return fail(MLBM_EINVAL, "null argument");
+// The three init phases shared by both ways of naming the state; `a` is rho4
+// (kFromDensity) or nu2 (kFromChemical).
+static int init_state(mlbm_handle h, int src, void* W, const double* a, const double* axis, const double* u,
+                      const double* T, void* stream) {
     if (int e = red_scratch(h)) return e;
     hipStream_t s = as_stream(stream);
     double r[kRedSlots];
     if (h->storage == MLBM_STORE_F16DEV) {
         // global means of the initial state (Eqs. GlobalDensity, GlobalVelocity, GlobalTotalEnergy)
-        HIP_TRY(launch_init(h->Q, h->storage, 0, W, rho4, u, T, h->kp, h->fp, h->d_partials, s));
+        HIP_TRY(launch_init(h->Q, h->storage, 0, src, W, a, axis, u, T, h->kp, h->fp, h->d_partials, s));
         HIP_TRY(launch_finalize(h->d_partials, kRedBlocks, kRedSlots, 0u, h->d_result, nullptr, 1.0, s));
         if (int e = read_result(h, r, s)) return e;
         if (int e = check_init_flags(r)) return e;
@@ -364,7 +364,7 @@ int mlbm_init_equilibrium(mlbm_handle h, void* W, const double* rho4, const doub
             for (int i = 0; i < h->Q; ++i) ref[k * h->Q + i] = h->kp.w[i] * rbar[k] * host_P(h, i, ubar, epsbar);
         set_f16(h, ref, 1.0);
         // largest scaled deviation max |a - R| / w_i fixes the power-of-two scale
-        HIP_TRY(launch_init(h->Q, h->storage, 1, W, rho4, u, T, h->kp, h->fp, h->d_partials, s));
+        HIP_TRY(launch_init(h->Q, h->storage, 1, src, W, a, axis, u, T, h->kp, h->fp, h->d_partials, s));
         HIP_TRY(launch_finalize(h->d_partials, kRedBlocks, kRedSlots, 1u, h->d_result, nullptr, 1.0, s));
         if (int e = read_result(h, r, s)) return e;
         if (int e = check_init_flags(r)) return e;
@@ -376,11 +376,25 @@ int mlbm_init_equilibrium(mlbm_handle h, void* W, const double* rho4, const doub
         }
         set_f16(h, ref, scale);
     }
-    HIP_TRY(launch_init(h->Q, h->storage, 2, W, rho4, u, T, h->kp, h->fp, h->d_partials, s));
+    HIP_TRY(launch_init(h->Q, h->storage, 2, src, W, a, axis, u, T, h->kp, h->fp, h->d_partials, s));
     HIP_TRY(launch_finalize(h->d_partials, kRedBlocks, kRedSlots, 0u, h->d_result, nullptr, 1.0, s));
     if (int e = read_result(h, r, s)) return e;
     if (int e = check_init_flags(r)) return e;
     return ok();
+}
+
+int mlbm_init_equilibrium(mlbm_handle h, void* W, const double* rho4, const double* u, const double* T,
+                          void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!W || !rho4 || !u || !T) return fail(MLBM_EINVAL, "null argument");
+    return init_state(h, kFromDensity, W, rho4, nullptr, u, T, stream);
+}
+
+int mlbm_init_chemical(mlbm_handle h, void* W, const double* nu, const double* axis, const double* u, const double* T,
+                       void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!W || !nu || !u || !T) return fail(MLBM_EINVAL, "null argument");
+    return init_state(h, kFromChemical, W, nu, axis, u, T, stream);
 }
 
 int mlbm_step(mlbm_handle h, void* W, void* scratch, int nsteps, void* stream) {

@@ -135,6 +135,14 @@ __device__ __forceinline__ bool channel_nu(double n, double beta, double& nu) {
     }
 }
 
+// n_{d,beta,mu} = (2 pi / beta)^(d/2) F_{d/2-1}(nu), nu = beta mu (Eq. nFDstdOmega).
+template <int D>
+__device__ __forceinline__ double channel_density(double beta, double nu) {
+    const double s = 2.0 * kPi / beta;
+    if constexpr (D == 2) return s * F0(nu);
+    else return s * sqrt(s) * half<1>(nu);
+}
+
 // eps_FD of Eq. energyFDstdOmega.
 template <int D>
 __device__ __forceinline__ double internal_energy(double beta, double nu_up, double nu_dn,

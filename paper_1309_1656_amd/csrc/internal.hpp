@@ -53,8 +53,10 @@ hipError_t launch_adjoint(int Q, int mode, bool wpull, const void* Wn, const voi
 // rho_k, 4..6 tr(rho) u, 7 total energy); phase 1: reduce max |a - R| / w_i
 // into slot 0 (max); phase 2: write W.  Slots 8, 9 count domain errors and
 // failed inversions in every phase.
-hipError_t launch_init(int Q, int mode, int phase, void* W, const double* rho4, const double* u,
-                       const double* T, const KParams& p, const FdParams& fp, double* partials,
+// how mlbm_init_* names the per-cell state
+enum InitSource { kFromDensity = 0, kFromChemical = 1 };
+hipError_t launch_init(int Q, int mode, int phase, int src, void* W, const double* a, const double* axis,
+                       const double* u, const double* T, const KParams& p, const FdParams& fp, double* partials,
                        hipStream_t s);
 
 // Reduce nblocks rows of `stride` partials (stride <= kRedSlots) to one

@@ -23,7 +23,7 @@ EXPORTS = (
     "mlbm_create", "mlbm_destroy", "mlbm_get_info", "mlbm_field_bytes", "mlbm_set_tau", "mlbm_set_eq_mode",
     "mlbm_init_equilibrium", "mlbm_step", "mlbm_collide", "mlbm_stream", "mlbm_moments", "mlbm_spin_loss",
     "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_set_f16_reference", "mlbm_set_launch",
-    "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_last_error",
+    "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_init_chemical", "mlbm_last_error",
 )
 
 
@@ -78,6 +78,7 @@ def load_library(path=LIB_PATH):
         "mlbm_set_launch": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "mlbm_set_magnetic_field": ([vp, dp], ctypes.c_int),
         "mlbm_set_magnetic_field_map": ([vp, vp], ctypes.c_int),
+        "mlbm_init_chemical": ([vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -243,6 +244,15 @@ def mlbm_init_equilibrium(h, W, rho4, u, T, stream=None):
     _check(load_library().mlbm_init_equilibrium(
         h.ptr, _field_ptr(h, W, "W"), _f64_ptr(h, rho4, 4, "rho4"), _f64_ptr(h, u, d, "u"),
         _f64_ptr(h, T, 1, "T"), _stream_ptr(stream)))
+    mlbm_get_info(h)
+
+
+def mlbm_init_chemical(h, W, nu, u, T, axis=None, stream=None):
+    """Equilibrium from nu = beta mu per spin channel ([2, *grid]) and an optional spin axis ([3, *grid])."""
+    d = h.info["d"]
+    _check(load_library().mlbm_init_chemical(
+        h.ptr, _field_ptr(h, W, "W"), _f64_ptr(h, nu, 2, "nu"), _f64_ptr(h, axis, 3, "axis"),
+        _f64_ptr(h, u, d, "u"), _f64_ptr(h, T, 1, "T"), _stream_ptr(stream)))
     mlbm_get_info(h)
 
 

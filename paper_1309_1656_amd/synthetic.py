@@ -131,6 +131,23 @@ def target_bloch_field(shape, seed, amplitude=0.3):
 
 
 # Workloads: (lattice Q, grid shape, tau, steps).  The grid shape is (y, x) or (z, y, x).
+def riemann_fields(shape=(2, 2048)):
+    """Initial data of the Riemann problem of Sec. 4 on a quasi-1D periodic grid.
+
+    Two equilibrated halves, separated at the middle of the x range (the
+    membrane at x = 0; the periodic wrap is a second, mirrored membrane):
+    left nu_up = -3/2, nu_dn = -5/2, right nu_up = -2, nu_dn = -3, with
+    beta = 1, u = 0 and the spin axis +z on both sides.  Returns nu [2, *grid]
+    (beta mu of the up and down channel), u_lat [2, *grid] and T [*grid].
+    """
+    nx = shape[-1]
+    left = np.arange(nx) < nx // 2
+    nu = np.empty((2,) + tuple(shape))
+    nu[0] = np.where(left, -1.5, -2.0)
+    nu[1] = np.where(left, -2.5, -3.0)
+    return {"nu": nu, "u_lat": np.zeros((2,) + tuple(shape)), "T": np.ones(shape)}
+
+
 WORKLOADS = {
     "d2q9_64": dict(Q=9, shape=(64, 64), tau=0.8, steps=100, seed=BASE_SEED + 1),
     "d2q9_1024_shear": dict(Q=9, shape=(1024, 1024), tau=0.6, steps=1000, seed=BASE_SEED + 2),
@@ -139,4 +156,6 @@ WORKLOADS = {
     "d3q19_64": dict(Q=19, shape=(64, 64, 64), tau=0.8, steps=200, seed=BASE_SEED + 4),
     "d2q9_512_adjoint": dict(Q=9, shape=(512, 512), tau=0.8, steps=200, seed=BASE_SEED + 5),
     "d2q9_16_adjoint": dict(Q=9, shape=(16, 16), tau=0.8, steps=10, seed=BASE_SEED + 5),
+    # Sec. 4 validation workloads
+    "d2q9_riemann": dict(Q=9, shape=(2, 2048), tau=10.0, steps=385, seed=None),
 }
