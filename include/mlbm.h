@@ -250,6 +250,24 @@ int mlbm_moments(mlbm_handle h, const void* W, double* rho4, double* u,
                  double* eps, double* global8, int64_t* n_neg_eig, void* stream);
 
 /*
+ * mlbm_relaxation -- how far field W is from the uniform state it relaxes to
+ * (Sec. 4, convergence to equilibrium), and the split of the global energy
+ * (Sec. 4, interference: the total is conserved, the internal part is not).
+ * The uniform state has the global averages rho_bar, u_bar, eps_tot_bar of
+ * Eqs. GlobalDensity, GlobalVelocity, GlobalTotalEnergy.  out[8] (host):
+ *   out[0] max over cells of ||rho(x) - rho_bar|| (spectral norm of the 2x2
+ *          Hermitian difference, (|d0| + |d|)/2 in Pauli coefficients d),
+ *   out[1] max |u(x) - u_bar|,   out[2] max |eps_tot(x) - eps_tot_bar|,
+ *          with eps_tot(x) = eps(x) + |u(x)|^2 / 2,
+ *   out[3] mean over cells of tr rho(x) eps(x)       (internal energy),
+ *   out[4] mean over cells of tr rho(x) |u(x)|^2 / 2 (kinetic energy),
+ *   out[5..7] root mean square over cells of the distances of out[0..2].
+ * Two reduction passes in fixed order (bitwise reproducible); synchronises
+ * `stream`.  Errors: MLBM_EINVAL (null W or out), MLBM_ENONFINITE, MLBM_EHIP.
+ */
+int mlbm_relaxation(mlbm_handle h, const void* W, double out[8], void* stream);
+
+/*
  * mlbm_spin_loss -- L = (1/N) sum_x |r(x) - r_target(x)|^2 with r the Bloch
  * vector of rho(x) = sum_i W_i(x), and its gradient with respect to W:
  *   r_target [3][N] double (device);

@@ -228,6 +228,32 @@ def global_means(lat, W):
     return np.concatenate([rho_mean, mom, [etot]])
 
 
+def relaxation(lat, W):
+    """Distances of every cell from the uniform state of the global averages
+    (Eqs. GlobalDensity, GlobalVelocity, GlobalTotalEnergy; Sec. 4, convergence
+    to equilibrium) and the global internal and kinetic energy (Sec. 4,
+    interference).  Returns the 8 numbers: max over cells of the spectral norm
+    of rho(x) - rho_bar, of |u(x) - u_bar| and of |eps_tot(x) - eps_tot_bar|;
+    mean of tr rho eps and of tr rho |u|^2 / 2; root mean squares of the three
+    distances.  rho_bar is the mean density matrix, u_bar = mean(tr rho u) /
+    mean(tr rho), eps_tot_bar = mean(tr rho eps_tot) / mean(tr rho).
+    """
+    rho, T, u, eps = moments(lat, W)
+    g = tuple(range(1, rho.ndim - 2 + 1))
+    axes = tuple(range(rho.ndim - 2))
+    rho_bar = rho.mean(axis=axes)
+    Tm = T.mean()
+    u_bar = (T[None] * u).mean(axis=tuple(range(1, u.ndim))) / Tm
+    uu = (u ** 2).sum(axis=0)
+    etot = eps + 0.5 * uu
+    etot_bar = (T * etot).mean() / Tm
+    drho = np.abs(np.linalg.eigvalsh(rho - rho_bar)).max(axis=-1)
+    du = np.sqrt(((u - u_bar.reshape((-1,) + (1,) * (u.ndim - 1))) ** 2).sum(axis=0))
+    de = np.abs(etot - etot_bar)
+    return np.array([drho.max(), du.max(), de.max(), (T * eps).mean(), (0.5 * T * uu).mean(),
+                     np.sqrt((drho ** 2).mean()), np.sqrt((du ** 2).mean()), np.sqrt((de ** 2).mean())])
+
+
 def count_negative_eigenvalues(W):
     """Number of populations W_i(x) with a negative eigenvalue (Sec. 3.2, last paragraph)."""
     ev = np.linalg.eigvalsh(W)

@@ -31,7 +31,7 @@ struct mlbm_ctx {
     int device = -1;
     double* d_partials = nullptr;   // reduction partials
     size_t partials_cap = 0;        // in doubles
-    double* d_result = nullptr;     // kRedSlots finalised values
+    double* d_result = nullptr;     // 2 kRedSlots finalised values (two chained reductions)
 };
 
 namespace {
@@ -109,7 +109,7 @@ int ensure_scratch(mlbm_ctx* h, size_t need) {
         h->d_partials = nullptr;
     }
     if (!h->d_result) {
-        if (hipMalloc(&h->d_result, kRedSlots * sizeof(double)) != hipSuccess)
+        if (hipMalloc(&h->d_result, 2 * kRedSlots * sizeof(double)) != hipSuccess)
             return fail(MLBM_ENOMEM, "cannot allocate %zu bytes of device memory", kRedSlots * sizeof(double));
     }
     if (hipMalloc(&h->d_partials, need * sizeof(double)) != hipSuccess) {
@@ -459,6 +459,31 @@ int mlbm_moments(mlbm_handle h, const void* W, double* rho4, double* u, double* 
     }
     if (n_neg_eig) *n_neg_eig = static_cast<int64_t>(r[8]);
     if (r[9] > 0) return fail(MLBM_ENONFINITE, "%.0f non-finite values in the field", r[9]);
+    return ok();
+}
+
+int mlbm_relaxation(mlbm_handle h, const void* W, double out[8], void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!W || !out) return fail(MLBM_EINVAL, "null argument");
+    if (int e = red_scratch(h)) return e;
+    hipStream_t s = as_stream(stream);
+    // pass 1: global sums into d_result[0..); pass 2 reads them on the device
+    HIP_TRY(launch_moments(h->Q, h->storage, W, nullptr, nullptr, nullptr, h->kp, h->d_partials, s));
+    HIP_TRY(launch_finalize(h->d_partials, kRedBlocks, kRedSlots, 0u, h->d_result, nullptr, 1.0, s));
+    HIP_TRY(launch_relaxation(h->Q, h->storage, W, h->d_result, h->kp, h->d_partials, s));
+    HIP_TRY(launch_finalize(h->d_partials, kRedBlocks, kRedSlots, 7u, h->d_result + kRedSlots, nullptr, 1.0, s));
+    double r[2 * kRedSlots];
+    HIP_TRY(hipMemcpyAsync(r, h->d_result, 2 * kRedSlots * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (r[9] > 0) return fail(MLBM_ENONFINITE, "%.0f non-finite values in the field", r[9]);
+    const double* q = r + kRedSlots;
+    const double invN = 1.0 / static_cast<double>(h->N);
+    out[0] = q[0];
+    out[1] = q[1];
+    out[2] = q[2];
+    out[3] = q[3] * invN;
+    out[4] = q[4] * invN;
+    for (int j = 5; j < 8; ++j) out[j] = std::sqrt(q[j] * invN);
     return ok();
 }
 

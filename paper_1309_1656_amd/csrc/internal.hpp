@@ -40,6 +40,8 @@ hipError_t launch_moments(int Q, int mode, const void* W, double* rho4, double* 
                           const KParams& p, double* partials, hipStream_t s);
 
 // Spin loss: slot 0 partial sum of |r - r_target|^2; optional adjoint seed.
+hipError_t launch_relaxation(int Q, int mode, const void* W, const double* g, const KParams& p, double* partials,
+                             hipStream_t s);
 hipError_t launch_spin_loss(int Q, int mode, const void* W, const double* r_target, void* lam,
                             const KParams& p, double* partials, hipStream_t s);
 

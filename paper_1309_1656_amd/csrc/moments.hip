@@ -72,6 +72,72 @@ k_moments(const typename Store<MODE>::T* __restrict__ W, double* __restrict__ rh
     block_reduce_store<0u>(acc, partials + blockIdx.x * kRedSlots);
 }
 
+// Distance of every cell from the uniform state of the global averages
+// (Eqs. GlobalDensity, GlobalVelocity, GlobalTotalEnergy), which is the state
+// the run converges to (Sec. 4, convergence to equilibrium), and the global
+// internal and kinetic energy (Sec. 4, interference: only their sum is
+// conserved).  g holds the sums of a k_moments pass already finalised:
+// g[0..3] sum rho, g[4..6] sum tr rho u, g[7] sum tr rho eps_tot.
+// Slots: 0 max ||rho - rho_bar|| (spectral norm), 1 max |u - u_bar|,
+// 2 max |eps_tot - eps_tot_bar|, 3 sum tr rho eps, 4 sum tr rho |u|^2 / 2,
+// 5..7 sums of the squares of the three distances.
+template <int Q, int MODE>
+__global__ void __launch_bounds__(kRedThreads)
+k_relaxation(const typename Store<MODE>::T* __restrict__ W, const double* __restrict__ g, const KParams p,
+             double* __restrict__ partials) {
+    constexpr int D = Lat<Q>::D;
+    const size_t N = static_cast<size_t>(p.ncell);
+    const double invN = 1.0 / static_cast<double>(N);
+    const double rho_bar[4] = {g[0] * invN, g[1] * invN, g[2] * invN, g[3] * invN};
+    const double u_bar[3] = {g[4] / g[0], g[5] / g[0], g[6] / g[0]};
+    const double etot_bar = g[7] / g[0];
+    double acc[kRedSlots];
+#pragma unroll
+    for (int s = 0; s < kRedSlots; ++s) acc[s] = 0.0;
+    for (size_t n = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; n < N;
+         n += static_cast<size_t>(gridDim.x) * blockDim.x) {
+        const size_t row = n / p.nx;
+        const int x = static_cast<int>(n - row * p.nx);
+        double rho[4] = {0.0, 0.0, 0.0, 0.0}, J[3] = {0.0, 0.0, 0.0}, K = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double a0 = static_cast<double>(decode<MODE>(W[fidx(Q, p.nx, row, 0, i, x)], 0, i, p));
+            rho[0] += a0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) J[c] += Lat<Q>::c(i, c) * a0;
+            K += csq<Q>(i) * a0;
+#pragma unroll
+            for (int k = 1; k < 4; ++k) rho[k] += static_cast<double>(decode<MODE>(W[fidx(Q, p.nx, row, k, i, x)], k, i, p));
+        }
+        const double T = rho[0];
+        double uu = 0.0, du2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double uc = (c < D) ? p.xi * J[c] / T : 0.0;
+            uu += uc * uc;
+            du2 += (uc - u_bar[c]) * (uc - u_bar[c]);
+        }
+        const double etot = p.half_xi2 * K;     // tr rho eps_tot of the cell
+        // (rho - rho_bar) = (d0 I + d . sigma) / 2 has eigenvalues (d0 +- |d|) / 2
+        const double d0 = rho[0] - rho_bar[0];
+        const double dv = sqrt((rho[1] - rho_bar[1]) * (rho[1] - rho_bar[1]) +
+                               (rho[2] - rho_bar[2]) * (rho[2] - rho_bar[2]) +
+                               (rho[3] - rho_bar[3]) * (rho[3] - rho_bar[3]));
+        const double drho = 0.5 * (fabs(d0) + dv);
+        const double du = sqrt(du2);
+        const double de = fabs(etot / T - etot_bar);
+        acc[0] = fmax(acc[0], drho);
+        acc[1] = fmax(acc[1], du);
+        acc[2] = fmax(acc[2], de);
+        acc[3] += etot - 0.5 * T * uu;
+        acc[4] += 0.5 * T * uu;
+        acc[5] += drho * drho;
+        acc[6] += du2;
+        acc[7] += de * de;
+    }
+    block_reduce_store<7u>(acc, partials + blockIdx.x * kRedSlots);
+}
+
 template <int Q, int MODE>
 __global__ void __launch_bounds__(kRedThreads)
 k_spin_loss(const typename Store<MODE>::T* __restrict__ W, const double* __restrict__ rt,
@@ -159,6 +225,26 @@ hipError_t launch_moments(int Q, int mode, const void* W, double* rho4, double* 
     if (mode == kF64) return moments_q<19, kF64>(W, rho4, u, eps, p, partials, s);
     if (mode == kF32) return moments_q<19, kF32>(W, rho4, u, eps, p, partials, s);
     return moments_q<19, kF16Dev>(W, rho4, u, eps, p, partials, s);
+}
+
+template <int Q, int MODE>
+static hipError_t relax_q(const void* W, const double* g, const KParams& p, double* partials, hipStream_t s) {
+    using T = typename Store<MODE>::T;
+    hipLaunchKernelGGL((k_relaxation<Q, MODE>), dim3(kRedBlocks), dim3(kRedThreads), 0, s,
+                       static_cast<const T*>(W), g, p, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_relaxation(int Q, int mode, const void* W, const double* g, const KParams& p, double* partials,
+                             hipStream_t s) {
+    if (Q == 9) {
+        if (mode == kF64) return relax_q<9, kF64>(W, g, p, partials, s);
+        if (mode == kF32) return relax_q<9, kF32>(W, g, p, partials, s);
+        return relax_q<9, kF16Dev>(W, g, p, partials, s);
+    }
+    if (mode == kF64) return relax_q<19, kF64>(W, g, p, partials, s);
+    if (mode == kF32) return relax_q<19, kF32>(W, g, p, partials, s);
+    return relax_q<19, kF16Dev>(W, g, p, partials, s);
 }
 
 template <int Q, int MODE>

@@ -23,7 +23,8 @@ EXPORTS = (
     "mlbm_create", "mlbm_destroy", "mlbm_get_info", "mlbm_field_bytes", "mlbm_set_tau", "mlbm_set_eq_mode",
     "mlbm_init_equilibrium", "mlbm_step", "mlbm_collide", "mlbm_stream", "mlbm_moments", "mlbm_spin_loss",
     "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_set_f16_reference", "mlbm_set_launch",
-    "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_init_chemical", "mlbm_last_error",
+    "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_init_chemical", "mlbm_relaxation",
+    "mlbm_last_error",
 )
 
 
@@ -79,6 +80,7 @@ def load_library(path=LIB_PATH):
         "mlbm_set_magnetic_field": ([vp, dp], ctypes.c_int),
         "mlbm_set_magnetic_field_map": ([vp, vp], ctypes.c_int),
         "mlbm_init_chemical": ([vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "mlbm_relaxation": ([vp, vp, dp, vp], ctypes.c_int),
         "mlbm_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -285,6 +287,17 @@ def mlbm_moments(h, W, rho4=None, u=None, eps=None, host=True, stream=None):
     if host:
         return np.array(g[:]), int(nneg.value)
     return None
+
+
+RELAXATION_KEYS = ("max_drho", "max_du", "max_detot", "internal_energy", "kinetic_energy",
+                   "rms_drho", "rms_du", "rms_detot")
+
+
+def mlbm_relaxation(h, W, stream=None):
+    """Distances from the uniform equilibrium and the energy split, as a dict (RELAXATION_KEYS)."""
+    out = (ctypes.c_double * 8)()
+    _check(load_library().mlbm_relaxation(h.ptr, _field_ptr(h, W, "W"), out, _stream_ptr(stream)))
+    return dict(zip(RELAXATION_KEYS, out[:]))
 
 
 def mlbm_spin_loss(h, W, r_target, loss=None, lam=None, stream=None):

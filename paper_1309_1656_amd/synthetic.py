@@ -148,6 +148,55 @@ def riemann_fields(shape=(2, 2048)):
     return {"nu": nu, "u_lat": np.zeros((2,) + tuple(shape)), "T": np.ones(shape)}
 
 
+def interference_fields(shape=(128, 128), sigma=6.0, amp=0.1, offset=18):
+    """Two wavelet-shaped packets that collide (Sec. 4, interference).
+
+    Packet 1 sits at (y, x) = (c - offset, c - offset), packet 2 at
+    (c + offset, c - offset), c the grid centre.  Each carries a Ricker
+    wavelet psi = (1 - r^2/sigma^2) exp(-r^2 / 2 sigma^2) of amplitude amp on
+    tr rho = 1; packet 1 is spin-polarised along +z, packet 2 along +y (Bloch
+    vector 0.3 tr rho times the Gaussian envelope); the velocity of a simple
+    acoustic wave, u_lat = 0.8 (delta rho / rho) along (1, 1)/sqrt 2 for
+    packet 1 and (1, -1)/sqrt 2 for packet 2, sends them toward each other.
+    T = 1.  Deterministic: no seed.
+    """
+    ny, nx = shape
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    cy, cx = ny / 2.0, nx / 2.0
+    packets = [((cy - offset, cx - offset), (1.0, 1.0), 2), ((cy + offset, cx - offset), (-1.0, 1.0), 1)]
+    trrho = np.ones(shape)
+    r = np.zeros((3,) + shape)
+    u_lat = np.zeros((2,) + shape)
+    bumps = []
+    for (py, px), _, _ in packets:
+        r2 = (y - py) ** 2 + (x - px) ** 2
+        env = np.exp(-r2 / (2 * sigma ** 2))
+        bumps.append((amp * (1 - r2 / sigma ** 2) * env, env))
+        trrho += bumps[-1][0]
+    for ((py, px), (dy, dx), comp), (dpsi, env) in zip(packets, bumps):
+        r[comp] += 0.3 * trrho * env
+        norm = np.hypot(dy, dx)
+        u_lat[0] += 0.8 * dpsi / trrho * dx / norm      # x component
+        u_lat[1] += 0.8 * dpsi / trrho * dy / norm      # y component
+    return {"trrho": trrho, "r": r, "u_lat": u_lat, "T": np.ones(shape)}
+
+
+def dichotomic_fields(shape=(32, 32, 32), amp=0.3):
+    """Uniform tr rho with spin domains of opposite z polarisation (Sec. 4,
+    convergence to equilibrium): r_z = amp tanh(4 sin(2 pi x/n) sin(2 pi y/n)
+    sin(2 pi z/n)), a smooth two-valued outline; u_lat along x proportional to
+    r_z with 0.05 at r_z = amp; T = 1.  Deterministic: no seed."""
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(*(np.arange(n, dtype=np.float64) for n in shape), indexing="ij")
+    s = np.sin(2 * np.pi * x / nx) * np.sin(2 * np.pi * y / ny) * np.sin(2 * np.pi * z / nz)
+    rz = amp * np.tanh(4.0 * s)
+    r = np.zeros((3,) + shape)
+    r[2] = rz
+    u_lat = np.zeros((3,) + shape)
+    u_lat[0] = 0.05 * rz / amp
+    return {"trrho": np.ones(shape), "r": r, "u_lat": u_lat, "T": np.ones(shape)}
+
+
 WORKLOADS = {
     "d2q9_64": dict(Q=9, shape=(64, 64), tau=0.8, steps=100, seed=BASE_SEED + 1),
     "d2q9_1024_shear": dict(Q=9, shape=(1024, 1024), tau=0.6, steps=1000, seed=BASE_SEED + 2),
@@ -158,4 +207,6 @@ WORKLOADS = {
     "d2q9_16_adjoint": dict(Q=9, shape=(16, 16), tau=0.8, steps=10, seed=BASE_SEED + 5),
     # Sec. 4 validation workloads
     "d2q9_riemann": dict(Q=9, shape=(2, 2048), tau=10.0, steps=385, seed=None),
+    "d2q9_interference": dict(Q=9, shape=(128, 128), tau=10.0, steps=54, seed=None),
+    "d3q19_convergence": dict(Q=19, shape=(32, 32, 32), tau=10.0, steps=300, seed=None),
 }
