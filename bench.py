@@ -74,7 +74,7 @@ def time_region(fn, reps=1):
     return a.elapsed_time(b) / reps
 
 
-def measure_step(shape, seed, tau, storage, steps, warmup, f, field=None):
+def measure_step(shape, seed, tau, storage, steps, warmup, f, field=None, isothermal=False, positivity=False):
     """MLUPS of mlbm_step(steps) and the fused kernel's average duration.
 
     field: None, "uniform" (one mu B for the grid) or "map" (mu B per cell,
@@ -86,6 +86,10 @@ def measure_step(shape, seed, tau, storage, steps, warmup, f, field=None):
     W = h.empty_field()
     mlbm.mlbm_init_equilibrium(h, W, *device_inputs(h, f))
     extra_bytes = 0
+    if isothermal:
+        mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_ISOTHERMAL)
+    if positivity:
+        mlbm.mlbm_set_positivity(h, 1)
     if field == "uniform":
         mlbm.mlbm_set_magnetic_field(h, [0.01, -0.02, 0.03])
     elif field == "map":
@@ -248,6 +252,14 @@ def main():
                                                         args.warmup, f, field=kind)
             log(f"  {extras['magnetic_f64'][kind]['mlups']:.0f} MLUPS, "
                 f"{extras['magnetic_f64'][kind]['fused_kernel_GBps']:.0f} GB/s")
+        extras["variants_f64"] = {}
+        for name, kw in (("isothermal", dict(isothermal=True)), ("positivity", dict(positivity=True)),
+                         ("isothermal_positivity", dict(isothermal=True, positivity=True))):
+            log(f"FP64 step, {name} variant")
+            extras["variants_f64"][name] = measure_step(shape, wl["seed"], tau, mlbm.MLBM_STORE_F64, args.steps,
+                                                        args.warmup, f, **kw)
+            log(f"  {extras['variants_f64'][name]['mlups']:.0f} MLUPS, "
+                f"{extras['variants_f64'][name]['fused_kernel_GBps']:.0f} GB/s")
         log("forward + adjoint rollout")
         extras["adjoint"] = measure_adjoint(args.warmup)
         log(f"  ratio {extras['adjoint']['ratio_to_f64_forward']:.2f}")

@@ -89,7 +89,7 @@ typedef struct mlbm_ctx* mlbm_handle;
 
 enum { MLBM_D2Q9 = 9, MLBM_D3Q19 = 19 };
 enum { MLBM_STORE_F64 = 0, MLBM_STORE_F32 = 1, MLBM_STORE_F16DEV = 2 };
-enum { MLBM_EQ_DIRECT = 0, MLBM_EQ_EIGEN = 1 };
+enum { MLBM_EQ_DIRECT = 0, MLBM_EQ_EIGEN = 1, MLBM_EQ_ISOTHERMAL = 2 };
 enum { MLBM_ORDER_AUTO = -1, MLBM_ORDER_NATURAL = 0, MLBM_ORDER_XCD_RANGE = 1, MLBM_ORDER_INTERLEAVE8 = 2 };
 enum {
     MLBM_OK = 0,
@@ -163,8 +163,35 @@ int mlbm_set_tau(mlbm_handle h, double tau);
  *     W_eq_i = w_i U diag(n_up, n_dn) U* P_i(u, eps_FD) is rebuilt from them.
  *     Equal to the direct form up to the inversion tolerance; a checking mode,
  *     many times slower.  Only for MLBM_STORE_F64 (else MLBM_EINVAL).
+ *   MLBM_EQ_ISOTHERMAL: the isothermal model the paper mentions and sets
+ *     aside (Sec. 3.1, paragraph on beta0 and mu0): every cell's equilibrium
+ *     has beta = beta0.  Per cell the eigenvalues n_up/dn = (tr rho +- |rho|)/2
+ *     are inverted to nu at beta0 (Eq. nFDstdOmega, in double) and the
+ *     Appendix coefficients take eps_FD(beta0; nu_up, nu_dn) of
+ *     Eq. energyFDstdOmega instead of the moment eps.  Mass and momentum are
+ *     conserved, energy is not.  Needs every cell's rho positive definite
+ *     (otherwise the result is not finite, which mlbm_moments reports).
+ * Errors: MLBM_EINVAL (bad mode; EIGEN without double storage or with the
+ * positivity limit; a mode other than DIRECT while a magnetic field is set).
  */
 int mlbm_set_eq_mode(mlbm_handle h, int mode);
+
+/*
+ * mlbm_set_positivity -- on = 1: positivity-limited relaxation, the
+ * adjustment the paper describes and avoids (Sec. 3.3, paragraph after the
+ * algorithm).  Per cell the collision uses the largest omega' in [0, omega]
+ * such that for every population i the smaller eigenvalue of
+ * (1 - omega') W_i + omega' W_eq_i is at least min(0, smaller eigenvalue of
+ * W_i): positive semidefinite populations stay so, and one that is already
+ * slightly negative (rounding) is not made worse.  The bound of each
+ * population is the first downward zero of a quadratic in omega' (the
+ * smaller eigenvalue is concave in omega'), the cell takes the minimum.
+ * Mass, momentum and energy stay conserved (omega' is one number per cell).
+ * on = 0 restores the plain BGK step.  Combines with MLBM_EQ_DIRECT and
+ * MLBM_EQ_ISOTHERMAL; not with MLBM_EQ_EIGEN, a magnetic field or the
+ * adjoint (MLBM_EINVAL).  The variant kernels use 64-cell blocks.
+ */
+int mlbm_set_positivity(mlbm_handle h, int on);
 
 /*
  * mlbm_init_equilibrium -- write into field W the discrete Fermi-Dirac
@@ -309,7 +336,8 @@ int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next,
  * i.e. every Bloch vector turns by 2 Delta t |mu B| about B; it commutes with
  * the BGK collision of a cell, so the order of the two does not matter.
  * Traces (density, momentum, energy) are untouched; tr(rho sigma) precesses.
- * Not combinable with MLBM_EQ_EIGEN or the adjoint (MLBM_EINVAL).
+ * Needs MLBM_EQ_DIRECT without the positivity limit; not combinable with the
+ * adjoint (MLBM_EINVAL).
  */
 int mlbm_set_magnetic_field(mlbm_handle h, const double mu_b[3]);
 

@@ -20,6 +20,7 @@ using namespace mlbm;
 
 struct mlbm_ctx {
     int Q = 0, d = 0, storage = 0, eq_mode = MLBM_EQ_DIRECT;
+    bool positivity = false;        // positivity-limited relaxation (mlbm_set_positivity)
     int64_t nx = 0, ny = 0, nz = 0, N = 0;
     double tau = 0.0, beta0 = 0.0;
     HostConst hc{};
@@ -208,6 +209,7 @@ int mlbm_create(mlbm_handle* out, int lattice, const int64_t dims[3], double tau
     for (int i = 0; i < 19; ++i) p.sc[i] = p.inv_sc[i] = 1.0f;
     p.field_mode = kFieldNone;
     p.bmap = nullptr;
+    p.variant = 0;
     for (int j = 0; j < 9; ++j) p.rot[j] = (j % 4 == 0) ? 1.0 : 0.0;
     gauss_legendre(kGL, h->fp.gl_x, h->fp.gl_w);
     *out = h;
@@ -273,14 +275,34 @@ int mlbm_set_tau(mlbm_handle h, double tau) {
     return ok();
 }
 
+static void update_variant(mlbm_handle h) {
+    h->kp.variant = (h->eq_mode == MLBM_EQ_ISOTHERMAL ? kVarIso : 0) | (h->positivity ? kVarPos : 0);
+}
+
 int mlbm_set_eq_mode(mlbm_handle h, int mode) {
     if (int e = check_handle(h)) return e;
-    if (mode != MLBM_EQ_DIRECT && mode != MLBM_EQ_EIGEN) return fail(MLBM_EINVAL, "bad equilibrium mode");
+    if (mode != MLBM_EQ_DIRECT && mode != MLBM_EQ_EIGEN && mode != MLBM_EQ_ISOTHERMAL)
+        return fail(MLBM_EINVAL, "bad equilibrium mode");
     if (mode == MLBM_EQ_EIGEN && h->storage != MLBM_STORE_F64)
         return fail(MLBM_EINVAL, "the eigen-channel mode needs double storage");
-    if (mode == MLBM_EQ_EIGEN && h->kp.field_mode != kFieldNone)
-        return fail(MLBM_EINVAL, "the eigen-channel mode does not take a magnetic field");
+    if (mode == MLBM_EQ_EIGEN && h->positivity)
+        return fail(MLBM_EINVAL, "the eigen-channel mode does not take the positivity limit");
+    if (mode != MLBM_EQ_DIRECT && h->kp.field_mode != kFieldNone)
+        return fail(MLBM_EINVAL, "the magnetic field needs the direct equilibrium mode");
     h->eq_mode = mode;
+    update_variant(h);
+    return ok();
+}
+
+int mlbm_set_positivity(mlbm_handle h, int on) {
+    if (int e = check_handle(h)) return e;
+    if (on != 0 && on != 1) return fail(MLBM_EINVAL, "positivity flag must be 0 or 1");
+    if (on && h->eq_mode == MLBM_EQ_EIGEN)
+        return fail(MLBM_EINVAL, "the eigen-channel mode does not take the positivity limit");
+    if (on && h->kp.field_mode != kFieldNone)
+        return fail(MLBM_EINVAL, "the positivity limit does not take a magnetic field");
+    h->positivity = on != 0;
+    update_variant(h);
     return ok();
 }
 
@@ -290,7 +312,8 @@ int mlbm_set_magnetic_field(mlbm_handle h, const double mu_b[3]) {
     if (!off) {
         if (!(std::isfinite(mu_b[0]) && std::isfinite(mu_b[1]) && std::isfinite(mu_b[2])))
             return fail(MLBM_EINVAL, "non-finite magnetic field");
-        if (h->eq_mode != MLBM_EQ_DIRECT) return fail(MLBM_EINVAL, "the eigen-channel mode does not take a magnetic field");
+        if (h->eq_mode != MLBM_EQ_DIRECT || h->positivity)
+            return fail(MLBM_EINVAL, "the magnetic field needs the direct equilibrium mode without the positivity limit");
     }
     KParams& p = h->kp;
     p.bmap = nullptr;
@@ -312,7 +335,8 @@ int mlbm_set_magnetic_field(mlbm_handle h, const double mu_b[3]) {
 
 int mlbm_set_magnetic_field_map(mlbm_handle h, const double* mu_b) {
     if (int e = check_handle(h)) return e;
-    if (mu_b && h->eq_mode != MLBM_EQ_DIRECT) return fail(MLBM_EINVAL, "the eigen-channel mode does not take a magnetic field");
+    if (mu_b && (h->eq_mode != MLBM_EQ_DIRECT || h->positivity))
+        return fail(MLBM_EINVAL, "the magnetic field needs the direct equilibrium mode without the positivity limit");
     h->kp.bmap = mu_b;
     h->kp.field_mode = mu_b ? kFieldMap : kFieldNone;
     return ok();
@@ -407,7 +431,7 @@ int mlbm_step(mlbm_handle h, void* W, void* scratch, int nsteps, void* stream) {
     const bool eig = h->eq_mode == MLBM_EQ_EIGEN;
     auto run = [&](StepKind kind, const void* a, void* b) -> hipError_t {
         if (eig && kind != StepKind::StreamOnly) return launch_step_eigen(kind, h->Q, a, b, h->kp, h->fp, nullptr, s);
-        return launch_step(kind, h->Q, h->storage, a, b, h->kp, h->launch, s);
+        return launch_step(kind, h->Q, h->storage, a, b, h->kp, h->fp, h->launch, s);
     };
     // After the collide-only pass and nsteps - 1 fused passes the
     // post-collision state sits in `scratch`; the stream-only pass then
@@ -430,7 +454,7 @@ int mlbm_collide(mlbm_handle h, const void* src, void* dst, void* stream) {
     if (!src || !dst) return fail(MLBM_EINVAL, "null field");
     hipStream_t s = as_stream(stream);
     if (h->eq_mode == MLBM_EQ_EIGEN) HIP_TRY(launch_step_eigen(StepKind::CollideOnly, h->Q, src, dst, h->kp, h->fp, nullptr, s));
-    else HIP_TRY(launch_step(StepKind::CollideOnly, h->Q, h->storage, src, dst, h->kp, h->launch, s));
+    else HIP_TRY(launch_step(StepKind::CollideOnly, h->Q, h->storage, src, dst, h->kp, h->fp, h->launch, s));
     return ok();
 }
 
@@ -438,7 +462,7 @@ int mlbm_stream(mlbm_handle h, const void* src, void* dst, void* stream) {
     if (int e = check_handle(h)) return e;
     if (!src || !dst) return fail(MLBM_EINVAL, "null field");
     if (src == dst) return fail(MLBM_EINVAL, "streaming needs distinct src and dst");
-    HIP_TRY(launch_step(StepKind::StreamOnly, h->Q, h->storage, src, dst, h->kp, h->launch, as_stream(stream)));
+    HIP_TRY(launch_step(StepKind::StreamOnly, h->Q, h->storage, src, dst, h->kp, h->fp, h->launch, as_stream(stream)));
     return ok();
 }
 
@@ -508,7 +532,8 @@ int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next, void
     if (int e = check_handle(h)) return e;
     if (!W_n || !lam_next || !lam_n) return fail(MLBM_EINVAL, "null field");
     if (h->storage == MLBM_STORE_F16DEV) return fail(MLBM_EINVAL, "the adjoint needs F64 or F32 storage");
-    if (h->eq_mode != MLBM_EQ_DIRECT) return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode");
+    if (h->eq_mode != MLBM_EQ_DIRECT || h->positivity)
+        return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode without the positivity limit");
     if (h->kp.field_mode != kFieldNone) return fail(MLBM_EINVAL, "the adjoint does not take a magnetic field");
     if (lam_n == W_n || lam_n == lam_next) return fail(MLBM_EINVAL, "lam_n must not alias the inputs");
     const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));
@@ -526,7 +551,8 @@ int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps,
     if (!W || !lam || !lam_tmp || (nsteps > 1 && !states)) return fail(MLBM_EINVAL, "null field");
     if (nsteps < 0) return fail(MLBM_EINVAL, "nsteps must be >= 0");
     if (h->storage == MLBM_STORE_F16DEV) return fail(MLBM_EINVAL, "the adjoint needs F64 or F32 storage");
-    if (h->eq_mode != MLBM_EQ_DIRECT) return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode");
+    if (h->eq_mode != MLBM_EQ_DIRECT || h->positivity)
+        return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode without the positivity limit");
     if (h->kp.field_mode != kFieldNone) return fail(MLBM_EINVAL, "the adjoint does not take a magnetic field");
     if (lam == lam_tmp || lam == W || lam_tmp == W) return fail(MLBM_EINVAL, "lam, lam_tmp and W must be distinct");
     if (nsteps == 0) return ok();
@@ -538,9 +564,9 @@ int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps,
     mlbm_field_bytes(h, &fb);
     char* st = static_cast<char*>(states);
     // forward recomputation: states[j] = post-collision state of step j (j = 0 .. nsteps - 2)
-    if (nsteps > 1) HIP_TRY(launch_step(StepKind::CollideOnly, h->Q, h->storage, W, st, h->kp, h->launch, s));
+    if (nsteps > 1) HIP_TRY(launch_step(StepKind::CollideOnly, h->Q, h->storage, W, st, h->kp, h->fp, h->launch, s));
     for (int j = 1; j < nsteps - 1; ++j)
-        HIP_TRY(launch_step(StepKind::Fused, h->Q, h->storage, st + (j - 1) * fb, st + j * fb, h->kp, h->launch, s));
+        HIP_TRY(launch_step(StepKind::Fused, h->Q, h->storage, st + (j - 1) * fb, st + j * fb, h->kp, h->fp, h->launch, s));
     // reverse sweep: step j reads W_j, gathered from states[j - 1] for j >= 1
     void* in = lam;
     void* out = lam_tmp;

@@ -68,7 +68,12 @@ struct KParams {
     int field_mode;
     double rot[9];
     const double* bmap;
+    // collision variants (Sec. 3.1 isothermal model, Sec. 3.3 positivity): bits kVar*
+    int variant;
 };
+
+// Collision variants of the step kernels.
+enum VariantBits { kVarIso = 1, kVarPos = 2 };
 
 template <int MODE> struct Store;
 template <> struct Store<kF64> { using T = double; using C = double; };

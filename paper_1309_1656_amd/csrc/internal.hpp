@@ -26,7 +26,7 @@ struct FdParams {
 };
 
 hipError_t launch_step(StepKind kind, int Q, int mode, const void* src, void* dst, const KParams& p,
-                       LaunchCfg want, hipStream_t s);
+                       const FdParams& fp, LaunchCfg want, hipStream_t s);
 
 // Eigen-channel variant of the fused / collide-only pass (double storage only).
 hipError_t launch_step_eigen(StepKind kind, int Q, const void* src, void* dst, const KParams& p,

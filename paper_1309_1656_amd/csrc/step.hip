@@ -19,6 +19,7 @@
 // a wave, so per-lane addresses are a scalar base plus x.  Stores are
 // non-temporal (the field is not re-read within the pass).
 #include "common.hpp"
+#include "fermi_device.hpp"
 #include "internal.hpp"
 
 namespace mlbm {
@@ -36,8 +37,10 @@ namespace mlbm {
 //   the rest and the 2D axis populations (+dE on the rest, -dE/(2D) on each
 //   axis population: mass and momentum unchanged).
 // Afterwards the conserved moments of S equal those of a up to one final float
-// rounding per value, which has no preferred sign.
-template <int Q, typename C>
+// rounding per value, which has no preferred sign.  ENERGY = false (isothermal
+// model, where the collision changes the energy on purpose) corrects mass and
+// momentum only.
+template <int Q, typename C, bool ENERGY = true>
 __device__ __forceinline__ void conserve(C (&S)[Q], const C (&a)[Q], int k) {
     constexpr int D = Lat<Q>::D;
     double dm = 0.0, dj[3] = {0.0, 0.0, 0.0}, dE = 0.0;
@@ -47,7 +50,7 @@ __device__ __forceinline__ void conserve(C (&S)[Q], const C (&a)[Q], int k) {
         dm += dd;
 #pragma unroll
         for (int c = 0; c < 3; ++c) dj[c] += Lat<Q>::c(i, c) * dd;
-        dE += csq<Q>(i) * dd;
+        if constexpr (ENERGY) dE += csq<Q>(i) * dd;
     }
     if (k != 0) {
         S[0] = static_cast<C>(static_cast<double>(S[0]) - dm);
@@ -103,6 +106,38 @@ __device__ __forceinline__ void block_order(int order, int nx, int ny, int bx, i
     z = static_cast<int>(row / static_cast<unsigned>(ny));
 }
 
+// Positivity-limited relaxation (Sec. 3.3, paragraph after the algorithm):
+// the largest w in [0, om] for which the collided population
+// (1 - w) a + w e keeps its smaller eigenvalue at or above min(0, that of a),
+// in Pauli coefficients (eigenvalues (x0 +- |x|)/2).  With
+// g(w) = a0 + w d0 - |a + w d|, d = e - a, and m = min(0, g(0)), g is concave,
+// so {w >= 0 : g(w) >= m} is an interval [0, w*].  If g(om) >= m the bound is
+// om; otherwise w* is where h(w) = (a0 - m + w d0)^2 - |a + w d|^2 first
+// crosses zero downward (h has the sign of g - m on [0, w*]): the smallest
+// root r in [0, om] of the quadratic with h'(r) < 0.  No such root (only
+// possible through rounding) gives the safe bound 0.
+template <typename C>
+__device__ __forceinline__ C psd_bound(C a0, C a1, C a2, C a3, C e0, C e1, C e2, C e3, C om) {
+    const C na = sqrt(a1 * a1 + a2 * a2 + a3 * a3);
+    const C m = fmin(C(0), a0 - na);
+    const C d0 = e0 - a0, d1 = e1 - a1, d2 = e2 - a2, d3 = e3 - a3;
+    const C f0 = a0 + om * d0, f1 = a1 + om * d1, f2 = a2 + om * d2, f3 = a3 + om * d3;
+    if (f0 - sqrt(f1 * f1 + f2 * f2 + f3 * f3) >= m) return om;
+    const C b0 = a0 - m;
+    const C A = d0 * d0 - (d1 * d1 + d2 * d2 + d3 * d3);
+    const C B = b0 * d0 - (a1 * d1 + a2 * d2 + a3 * d3);
+    const C Cc = fmax(C(0), b0 * b0 - na * na);
+    const C disc = B * B - A * Cc;
+    if (!(disc >= C(0))) return C(0);
+    const C q = -(B + copysign(sqrt(disc), B));
+    const C r1 = (A != C(0)) ? q / A : C(-1);
+    const C r2 = (q != C(0)) ? Cc / q : C(-1);
+    C best = C(-1);
+    if (r1 >= C(0) && r1 <= om && A * r1 + B < C(0)) best = r1;
+    if (r2 >= C(0) && r2 <= om && A * r2 + B < C(0)) best = (best < C(0)) ? r2 : fmin(best, r2);
+    return best < C(0) ? C(0) : best;
+}
+
 // Row k of the rotation of the Bloch vector produced by the magnetic-field
 // commutator -i [mu sigma.B, W] over one time step (Sec. 5, Eq. sigmaB_comm):
 // W -> U W U*, U = exp(-i Delta t sigma.(mu B)), turns every Bloch vector by
@@ -125,10 +160,10 @@ __device__ __forceinline__ void rotation_row(const double b[3], int k, double r[
     for (int l = 0; l < 3; ++l) r[l] = ((k == l) ? cs : 0.0) + sn * cx[k][l] + (1.0 - cs) * n[k] * n[l];
 }
 
-template <int Q, int MODE, bool PULL, bool COLL, int BX, int FIELD>
+template <int Q, int MODE, bool PULL, bool COLL, int BX, int FIELD, int VAR>
 __global__ void __launch_bounds__(BX * 4)
 k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T* __restrict__ dst,
-       const KParams p, const int order) {
+       const KParams p, const int order, const FdParams fp) {
     using T = typename Store<MODE>::T;
     using C = typename Store<MODE>::C;
     constexpr int D = Lat<Q>::D;
@@ -174,8 +209,13 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
         return;
     } else {
         // q_i of the trace wave; with a field the same LDS is reused for the
-        // exchange of the three Bloch channels (3 Q BX values)
-        __shared__ C lds[(FIELD != kFieldNone ? 3 : 1) * Q * BX];
+        // exchange of the three Bloch channels (3 Q BX values).  The
+        // positivity variant also hands the Bloch channels to the trace wave.
+        constexpr bool kIso = (VAR & kVarIso) != 0, kPos = (VAR & kVarPos) != 0;
+        static_assert(VAR == 0 || FIELD == kFieldNone, "variants and the field are exclusive");
+        __shared__ C lds[(FIELD != kFieldNone ? 3 : (kPos ? 4 : 1)) * Q * BX];
+        __shared__ double rsh[VAR != 0 ? 3 : 1][BX];      // rho_k of the Bloch waves
+        __shared__ C omsh[kPos ? BX : 1];                 // per-cell relaxation rate
         C (*qs)[BX] = reinterpret_cast<C (*)[BX]>(lds);
         C a[Q];
         double rk = 0.0;
@@ -183,6 +223,17 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
         for (int i = 0; i < Q; ++i) {
             a[i] = decode<MODE>(raw[i], k, i, p);
             rk += static_cast<double>(a[i]);
+        }
+        if constexpr (VAR != 0) {
+            if (k > 0) {
+                rsh[k - 1][lx] = rk;
+                if constexpr (kPos) {
+                    C (*ab)[Q][BX] = reinterpret_cast<C (*)[Q][BX]>(lds + Q * BX);
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) ab[k - 1][i][lx] = a[i];
+                }
+            }
+            __syncthreads();
         }
         if (k == 0) {
             // moments (Eq. DiscrAvr) in double; sums over c_i in {0, +-1}
@@ -198,7 +249,16 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
             const double invT = 1.0 / rk;
             const double u0 = p.xi * J0 * invT, u1 = p.xi * J1 * invT, u2 = (D == 3) ? p.xi * J2 * invT : 0.0;
             const double uu = u0 * u0 + u1 * u1 + u2 * u2;
-            const double eps = p.half_xi2 * K * invT - 0.5 * uu;
+            double eps = p.half_xi2 * K * invT - 0.5 * uu;
+            if constexpr (kIso) {
+                // isothermal model: the Fermi-Dirac state at beta = beta0 with the
+                // cell's density matrix, eigenvalues (tr rho +- |rho|)/2
+                const double rv = sqrt(rsh[0][lx] * rsh[0][lx] + rsh[1][lx] * rsh[1][lx] + rsh[2][lx] * rsh[2][lx]);
+                double nu_up = 0.0, nu_dn = 0.0;
+                fd::channel_nu<D>(0.5 * (rk + rv), p.beta0, nu_up);
+                fd::channel_nu<D>(0.5 * (rk - rv), p.beta0, nu_dn);
+                eps = fd::internal_energy<D>(p.beta0, nu_up, nu_dn, fp);
+            }
             // polynomial factor (Eq. WeqAlgo, Appendix), with v = beta0 xi u so that
             // beta0 e_i.u = c_i.v:
             //   P_i = alpha1 + alpha5 beta0 |u|^2/2 + alpha2 beta0 xi^2 |c_i|^2 / 2
@@ -210,6 +270,7 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
             const C v1 = static_cast<C>(p.beta0 * p.xi * u1);
             const C v2 = static_cast<C>(p.beta0 * p.xi * u2);
             const C a3 = cst<C>(p.a3, p.a3f), a4 = cst<C>(p.a4, p.a4f);
+            C wP[kPos ? Q : 1];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 C cv = C(0);
@@ -218,17 +279,35 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
                 if (Lat<Q>::c(i, 2) == 1) cv += v2; else if (Lat<Q>::c(i, 2) == -1) cv -= v2;
                 C P = A + cv * (a3 + a4 * cv);
                 if (csq<Q>(i) == 1) P += B; else if (csq<Q>(i) == 2) P += C(2) * B;
-                qs[i][lx] = omw_of<C>(p, i) * P;
+                if constexpr (kPos) wP[i] = static_cast<C>(p.w[i]) * P;
+                else qs[i][lx] = omw_of<C>(p, i) * P;
+            }
+            if constexpr (kPos) {
+                // the equilibrium of population i is wP_i rho (Eq. WeqAlgo)
+                C (*ab)[Q][BX] = reinterpret_cast<C (*)[Q][BX]>(lds + Q * BX);
+                const C r0 = static_cast<C>(rk), r1 = static_cast<C>(rsh[0][lx]), r2 = static_cast<C>(rsh[1][lx]),
+                        r3 = static_cast<C>(rsh[2][lx]);
+                const C om = static_cast<C>(p.om);
+                C omc = om;
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    omc = fmin(omc, psd_bound<C>(a[i], ab[0][i][lx], ab[1][i][lx], ab[2][i][lx], wP[i] * r0,
+                                                 wP[i] * r1, wP[i] * r2, wP[i] * r3, om));
+                omsh[lx] = omc;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) qs[i][lx] = omc * wP[i];
             }
         }
         __syncthreads();
         // collision (Eq. CollisionStep) of this wave's channel
         const C r = static_cast<C>(rk);
-        const C omm = cst<C>(p.one_m_om, p.one_m_omf);
+        C omm;
+        if constexpr (kPos) omm = C(1) - omsh[lx];
+        else omm = cst<C>(p.one_m_om, p.one_m_omf);
         C S[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) S[i] = omm * a[i] + qs[i][lx] * r;
-        if constexpr (MODE == kF32) conserve<Q>(S, a, k);
+        if constexpr (MODE == kF32) conserve<Q, C, !kIso>(S, a, k);
         if constexpr (FIELD != kFieldNone) {
             // magnetic precession of the Bloch components; it commutes with the
             // BGK collision cell by cell, so applying it afterwards is exact
@@ -284,48 +363,56 @@ LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want) {
     return c;
 }
 
-template <int Q, int MODE, bool PULL, bool COLL, int FIELD>
-static hipError_t launch(const void* src, void* dst, const KParams& p, LaunchCfg c, hipStream_t s) {
+template <int Q, int MODE, bool PULL, bool COLL, int FIELD, int VAR = 0>
+static hipError_t launch(const void* src, void* dst, const KParams& p, const FdParams& fp, LaunchCfg c,
+                         hipStream_t s) {
     using T = typename Store<MODE>::T;
+    if constexpr (VAR != 0) c.bx = 64;        // the variants are built for 64-cell blocks only
     const dim3 grd(static_cast<unsigned>((p.nx + c.bx - 1) / c.bx) * p.ny * p.nz);
-    if (c.bx == 64)
-        hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 64, FIELD>), grd, dim3(64, 4), 0, s,
-                           static_cast<const T*>(src), static_cast<T*>(dst), p, c.order);
-    else
-        hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 128, FIELD>), grd, dim3(128, 4), 0, s,
-                           static_cast<const T*>(src), static_cast<T*>(dst), p, c.order);
+    if (c.bx == 64) {
+        hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 64, FIELD, VAR>), grd, dim3(64, 4), 0, s,
+                           static_cast<const T*>(src), static_cast<T*>(dst), p, c.order, fp);
+    } else if constexpr (VAR == 0) {
+        hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 128, FIELD, 0>), grd, dim3(128, 4), 0, s,
+                           static_cast<const T*>(src), static_cast<T*>(dst), p, c.order, fp);
+    }
     return hipGetLastError();
 }
 
 template <int Q, int MODE, bool PULL>
-static hipError_t launch_coll(const void* src, void* dst, const KParams& p, LaunchCfg c, hipStream_t s) {
-    if (p.field_mode == kFieldUniform) return launch<Q, MODE, PULL, true, kFieldUniform>(src, dst, p, c, s);
-    if (p.field_mode == kFieldMap) return launch<Q, MODE, PULL, true, kFieldMap>(src, dst, p, c, s);
-    return launch<Q, MODE, PULL, true, kFieldNone>(src, dst, p, c, s);
+static hipError_t launch_coll(const void* src, void* dst, const KParams& p, const FdParams& fp, LaunchCfg c,
+                              hipStream_t s) {
+    if (p.variant == kVarIso) return launch<Q, MODE, PULL, true, kFieldNone, kVarIso>(src, dst, p, fp, c, s);
+    if (p.variant == kVarPos) return launch<Q, MODE, PULL, true, kFieldNone, kVarPos>(src, dst, p, fp, c, s);
+    if (p.variant == (kVarIso | kVarPos))
+        return launch<Q, MODE, PULL, true, kFieldNone, kVarIso | kVarPos>(src, dst, p, fp, c, s);
+    if (p.field_mode == kFieldUniform) return launch<Q, MODE, PULL, true, kFieldUniform>(src, dst, p, fp, c, s);
+    if (p.field_mode == kFieldMap) return launch<Q, MODE, PULL, true, kFieldMap>(src, dst, p, fp, c, s);
+    return launch<Q, MODE, PULL, true, kFieldNone>(src, dst, p, fp, c, s);
 }
 
 template <int Q, int MODE>
-static hipError_t dispatch_kind(StepKind kind, const void* src, void* dst, const KParams& p, LaunchCfg c,
-                                hipStream_t s) {
+static hipError_t dispatch_kind(StepKind kind, const void* src, void* dst, const KParams& p, const FdParams& fp,
+                                LaunchCfg c, hipStream_t s) {
     switch (kind) {
-        case StepKind::Fused: return launch_coll<Q, MODE, true>(src, dst, p, c, s);
-        case StepKind::CollideOnly: return launch_coll<Q, MODE, false>(src, dst, p, c, s);
-        case StepKind::StreamOnly: return launch<Q, MODE, true, false, kFieldNone>(src, dst, p, c, s);
+        case StepKind::Fused: return launch_coll<Q, MODE, true>(src, dst, p, fp, c, s);
+        case StepKind::CollideOnly: return launch_coll<Q, MODE, false>(src, dst, p, fp, c, s);
+        case StepKind::StreamOnly: return launch<Q, MODE, true, false, kFieldNone>(src, dst, p, fp, c, s);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_step(StepKind kind, int Q, int mode, const void* src, void* dst, const KParams& p,
-                       LaunchCfg want, hipStream_t s) {
+                       const FdParams& fp, LaunchCfg want, hipStream_t s) {
     const LaunchCfg c = step_launch(p.nx, p.ny, p.nz, Q, mode, want);
     if (Q == 9) {
-        if (mode == kF64) return dispatch_kind<9, kF64>(kind, src, dst, p, c, s);
-        if (mode == kF32) return dispatch_kind<9, kF32>(kind, src, dst, p, c, s);
-        return dispatch_kind<9, kF16Dev>(kind, src, dst, p, c, s);
+        if (mode == kF64) return dispatch_kind<9, kF64>(kind, src, dst, p, fp, c, s);
+        if (mode == kF32) return dispatch_kind<9, kF32>(kind, src, dst, p, fp, c, s);
+        return dispatch_kind<9, kF16Dev>(kind, src, dst, p, fp, c, s);
     }
-    if (mode == kF64) return dispatch_kind<19, kF64>(kind, src, dst, p, c, s);
-    if (mode == kF32) return dispatch_kind<19, kF32>(kind, src, dst, p, c, s);
-    return dispatch_kind<19, kF16Dev>(kind, src, dst, p, c, s);
+    if (mode == kF64) return dispatch_kind<19, kF64>(kind, src, dst, p, fp, c, s);
+    if (mode == kF32) return dispatch_kind<19, kF32>(kind, src, dst, p, fp, c, s);
+    return dispatch_kind<19, kF16Dev>(kind, src, dst, p, fp, c, s);
 }
 
 }  // namespace mlbm

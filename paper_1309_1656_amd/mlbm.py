@@ -13,7 +13,7 @@ import numpy as np
 
 MLBM_D2Q9, MLBM_D3Q19 = 9, 19
 MLBM_STORE_F64, MLBM_STORE_F32, MLBM_STORE_F16DEV = 0, 1, 2
-MLBM_EQ_DIRECT, MLBM_EQ_EIGEN = 0, 1
+MLBM_EQ_DIRECT, MLBM_EQ_EIGEN, MLBM_EQ_ISOTHERMAL = 0, 1, 2
 MLBM_ORDER_AUTO, MLBM_ORDER_NATURAL, MLBM_ORDER_XCD_RANGE, MLBM_ORDER_INTERLEAVE8 = -1, 0, 1, 2
 MLBM_OK, MLBM_EINVAL, MLBM_EDOMAIN, MLBM_EHIP, MLBM_ENOMEM, MLBM_ENONFINITE, MLBM_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 
@@ -23,7 +23,7 @@ EXPORTS = (
     "mlbm_create", "mlbm_destroy", "mlbm_get_info", "mlbm_field_bytes", "mlbm_set_tau", "mlbm_set_eq_mode",
     "mlbm_init_equilibrium", "mlbm_step", "mlbm_collide", "mlbm_stream", "mlbm_moments", "mlbm_spin_loss",
     "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_set_f16_reference", "mlbm_set_launch",
-    "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_init_chemical", "mlbm_relaxation",
+    "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_init_chemical", "mlbm_relaxation", "mlbm_set_positivity",
     "mlbm_last_error",
 )
 
@@ -81,6 +81,7 @@ def load_library(path=LIB_PATH):
         "mlbm_set_magnetic_field_map": ([vp, vp], ctypes.c_int),
         "mlbm_init_chemical": ([vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_relaxation": ([vp, vp, dp, vp], ctypes.c_int),
+        "mlbm_set_positivity": ([vp, ctypes.c_int], ctypes.c_int),
         "mlbm_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -330,6 +331,10 @@ def mlbm_set_magnetic_field_map(h, mu_b):
     ptr = _f64_ptr(h, mu_b, 3, "mu_b")
     _check(load_library().mlbm_set_magnetic_field_map(h.ptr, ptr))
     h._field_map = mu_b          # keep the device memory alive while the handle uses it
+
+
+def mlbm_set_positivity(h, on):
+    _check(load_library().mlbm_set_positivity(h.ptr, int(on)))
 
 
 def mlbm_set_launch(h, block_x=0, order=MLBM_ORDER_AUTO):

@@ -145,3 +145,29 @@ def test_magnetic_field_validation():
     assert lib.mlbm_adjoint_step(h.ptr, buf[0], buf[1], buf[2], None, None) == mlbm.MLBM_EINVAL
     mlbm.mlbm_set_magnetic_field(h, None)
     assert lib.mlbm_set_magnetic_field(None, None) == mlbm.MLBM_EINVAL
+
+
+def test_variant_validation():
+    lib = mlbm.load_library()
+    h = mlbm.mlbm_create(9, (8, 8, 1), 0.8, 1.0, mlbm.MLBM_STORE_F64)
+    mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_ISOTHERMAL)
+    assert h.info["eq_mode"] == mlbm.MLBM_EQ_ISOTHERMAL
+    with pytest.raises(mlbm.MlbmError):
+        mlbm.mlbm_set_magnetic_field(h, [0.1, 0.0, 0.0])
+    buf = [ctypes.c_void_p(4096 * (j + 1)) for j in range(3)]
+    assert lib.mlbm_adjoint_step(h.ptr, buf[0], buf[1], buf[2], None, None) == mlbm.MLBM_EINVAL
+    mlbm.mlbm_set_positivity(h, 1)
+    with pytest.raises(mlbm.MlbmError):
+        mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_EIGEN)
+    mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_DIRECT)
+    assert lib.mlbm_adjoint_step(h.ptr, buf[0], buf[1], buf[2], None, None) == mlbm.MLBM_EINVAL
+    with pytest.raises(mlbm.MlbmError):
+        mlbm.mlbm_set_positivity(h, 2)
+    mlbm.mlbm_set_positivity(h, 0)
+    mlbm.mlbm_set_magnetic_field(h, [0.1, 0.0, 0.0])
+    with pytest.raises(mlbm.MlbmError):
+        mlbm.mlbm_set_positivity(h, 1)
+    with pytest.raises(mlbm.MlbmError):
+        mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_ISOTHERMAL)
+    with pytest.raises(mlbm.MlbmError):
+        mlbm.mlbm_set_eq_mode(h, 3)
