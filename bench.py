@@ -161,6 +161,36 @@ def measure_adjoint(warmup):
             "grad_tau": float(tau_t.grad), "grad_W0_norm": float(W0.grad.norm())}
 
 
+def measure_launch_bound():
+    """The Riemann workload (D2Q9 2048 x 2, 385 steps): one mlbm_step call
+    launched eagerly against the same call captured once in a HIP graph."""
+    import torch
+    from paper_1309_1656_amd import mlbm, synthetic
+    wl = synthetic.WORKLOADS["d2q9_riemann"]
+    f = synthetic.riemann_fields(wl["shape"])
+    h = mlbm.mlbm_create(9, dims_of(wl["shape"]), wl["tau"], 1.0, mlbm.MLBM_STORE_F64)
+    W = h.empty_field()
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    mlbm.mlbm_init_chemical(h, W, to(f["nu"]), to(h.info["xi"] * f["u_lat"]), to(f["T"]))
+    tmp = h.empty_field()
+    n = wl["steps"]
+    mlbm.mlbm_step(h, W, tmp, 5)
+    t_eager = time_region(lambda: mlbm.mlbm_step(h, W, tmp, n), reps=3)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        mlbm.mlbm_step(h, W, tmp, 2)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        mlbm.mlbm_step(h, W, tmp, n)
+    g.replay()
+    t_graph = time_region(g.replay, reps=3)
+    N = int(np.prod(wl["shape"]))
+    return {"workload": "D2Q9 2048x2 Riemann problem, 385 steps, FP64", "eager_ms": t_eager, "graph_ms": t_graph,
+            "eager_mlups": N * n / (t_eager * 1e-3) / 1e6, "graph_mlups": N * n / (t_graph * 1e-3) / 1e6}
+
+
 def copy_bandwidth():
     import torch
     n = 1 << 28   # 2 GiB of float64 each way
@@ -260,6 +290,9 @@ def main():
                                                         args.warmup, f, **kw)
             log(f"  {extras['variants_f64'][name]['mlups']:.0f} MLUPS, "
                 f"{extras['variants_f64'][name]['fused_kernel_GBps']:.0f} GB/s")
+        log("launch-bound Riemann workload, eager and graph")
+        extras["launch_bound"] = measure_launch_bound()
+        log(f"  eager {extras['launch_bound']['eager_ms']:.3f} ms, graph {extras['launch_bound']['graph_ms']:.3f} ms")
         log("forward + adjoint rollout")
         extras["adjoint"] = measure_adjoint(args.warmup)
         log(f"  ratio {extras['adjoint']['ratio_to_f64_forward']:.2f}")
