@@ -35,15 +35,48 @@ __device__ __forceinline__ double logistic(double z) {
     return e / (1.0 + e);
 }
 
-// j^(-s) for s = TWO_S / 2.
+// j^(-s) for s = TWO_S / 2 and j = 1..60, tabulated at compile time (square
+// roots by Newton's iteration to its fixed point) so that the series below
+// spend no division or square root per term.
+constexpr double const_sqrt(double x) {
+    double g = x > 1.0 ? x : 1.0;
+    for (int i = 0; i < 200; ++i) {
+        const double n = 0.5 * (g + x / g);
+        if (n == g) break;
+        g = n;
+    }
+    return g;
+}
+
+constexpr int kSeriesTerms = 60;
+
+template <int TWO_S>
+struct JpowTable {
+    double v[kSeriesTerms + 1];
+    constexpr JpowTable() : v() {
+        for (int j = 1; j <= kSeriesTerms; ++j) {
+            double p = 1.0;
+            for (int r = 0; r < TWO_S / 2; ++r) p *= j;
+            if (TWO_S & 1) p *= const_sqrt(static_cast<double>(j));
+            v[j] = 1.0 / p;
+        }
+    }
+};
+
+__constant__ const JpowTable<1> kJpow1{};
+__constant__ const JpowTable<3> kJpow3{};
+__constant__ const JpowTable<4> kJpow4{};
+__constant__ const JpowTable<5> kJpow5{};
+__constant__ const JpowTable<7> kJpow7{};
+
 template <int TWO_S>
 __device__ __forceinline__ double jpow_inv(int j) {
-    const double dj = static_cast<double>(j);
-    double p = 1.0;
-#pragma unroll
-    for (int r = 0; r < TWO_S / 2; ++r) p *= dj;
-    if (TWO_S & 1) p *= sqrt(dj);
-    return 1.0 / p;
+    static_assert(TWO_S == 1 || TWO_S == 3 || TWO_S == 4 || TWO_S == 5 || TWO_S == 7, "no table for this order");
+    if constexpr (TWO_S == 1) return kJpow1.v[j];
+    else if constexpr (TWO_S == 3) return kJpow3.v[j];
+    else if constexpr (TWO_S == 4) return kJpow4.v[j];
+    else if constexpr (TWO_S == 5) return kJpow5.v[j];
+    else return kJpow7.v[j];
 }
 
 // sum_{j>=1} (-1)^(j+1) e^(j x) / j^s, s = TWO_S / 2, for x <= -1.
@@ -51,13 +84,29 @@ template <int TWO_S>
 __device__ double series(double x) {
     const double t = exp(x);
     double pj = t, sum = 0.0;
-    for (int j = 1; j <= 60; ++j) {
+    for (int j = 1; j <= kSeriesTerms; ++j) {
         const double term = pj * jpow_inv<TWO_S>(j);
         sum += (j & 1) ? term : -term;
         if (term <= 1e-18 * sum) break;
         pj *= t;
     }
     return sum;
+}
+
+// Two series of the same argument in one pass (shared powers of e^x).
+template <int TWO_A, int TWO_B>
+__device__ void series_pair(double x, double& sa, double& sb) {
+    const double t = exp(x);
+    double pj = t;
+    sa = 0.0;
+    sb = 0.0;
+    for (int j = 1; j <= kSeriesTerms; ++j) {
+        const double ta = pj * jpow_inv<TWO_A>(j), tb = pj * jpow_inv<TWO_B>(j);
+        sa += (j & 1) ? ta : -ta;
+        sb += (j & 1) ? tb : -tb;
+        if (ta <= 1e-18 * sa && tb <= 1e-18 * sb) break;
+        pj *= t;
+    }
 }
 
 // F_{M - 1/2}(x) by the trapezoidal rule described above, x > -1.
@@ -141,6 +190,49 @@ __device__ __forceinline__ double channel_density(double beta, double nu) {
     const double s = 2.0 * kPi / beta;
     if constexpr (D == 2) return s * F0(nu);
     else return s * sqrt(s) * half<1>(nu);
+}
+
+// Isothermal model: eps_FD at inverse temperature beta of the channel
+// densities n_up, n_dn (Eq. nFDstdOmega inverted, then Eq. energyFDstdOmega).
+// With c = F_{d/2-1}(nu) = n (beta / 2 pi)^(d/2) known exactly, the
+// denominator needs no evaluation: eps = (d/2) sum F_{d/2}(nu) / (beta sum c).
+// 2D: nu = log(expm1(c)) in closed form.  3D: Newton on F_{1/2}(nu) = c with
+// F_{1/2} and F_{-1/2} from one series pass, started at the dilute expansion
+// nu = log c + c / 2^(3/2) (F_{1/2} = e^nu - e^(2 nu) / 2^(3/2) + ...).
+__device__ __forceinline__ bool invert_half_fast(double c, double& nu) {
+    nu = (c < 0.5) ? log(c) + 0.35355339059327376220 * c : (c < 1.0 ? log(c) : pow(c * 1.32934038817913702047, 2.0 / 3.0));
+    for (int it = 0; it < 60; ++it) {
+        double f, df;
+        if (nu <= -1.0) series_pair<3, 1>(nu, f, df);
+        else { f = half<1>(nu); df = half<0>(nu); }
+        const double d = (f - c) / df;
+        nu -= d;
+        if (!isfinite(nu)) return false;
+        if (fabs(d) <= 2e-15 * fmax(1.0, fabs(nu))) return true;
+    }
+    return false;
+}
+
+// One channel of the isothermal energy: F_{d/2}(nu) for the channel density n
+// at inverse temperature beta (NaN if the inversion fails).
+template <int D>
+__device__ __forceinline__ double iso_channel(double beta, double n, const FdParams& fp) {
+    const double s = beta / (2.0 * kPi);
+    if constexpr (D == 2) {
+        return F1(log(expm1(n * s)), fp);
+    } else {
+        double nu = 0.0;
+        if (!invert_half_fast(n * s * sqrt(s), nu)) return __builtin_nan("");
+        return half<2>(nu);
+    }
+}
+
+// eps_FD from the two channels' F_{d/2}(nu): (d/2) sum F_{d/2} / (beta sum c).
+template <int D>
+__device__ __forceinline__ double iso_energy(double beta, double n_up, double n_dn, double f_up, double f_dn) {
+    const double s = beta / (2.0 * kPi);
+    const double sd = (D == 2) ? s : s * sqrt(s);
+    return 0.5 * D * (f_up + f_dn) / (beta * sd * (n_up + n_dn));
 }
 
 // eps_FD of Eq. energyFDstdOmega.

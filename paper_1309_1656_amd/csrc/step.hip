@@ -214,7 +214,8 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
         constexpr bool kIso = (VAR & kVarIso) != 0, kPos = (VAR & kVarPos) != 0;
         static_assert(VAR == 0 || FIELD == kFieldNone, "variants and the field are exclusive");
         __shared__ C lds[(FIELD != kFieldNone ? 3 : (kPos ? 4 : 1)) * Q * BX];
-        __shared__ double rsh[VAR != 0 ? 3 : 1][BX];      // rho_k of the Bloch waves
+        __shared__ double rsh[VAR != 0 ? 4 : 1][BX];      // rho_k of the Bloch waves; tr rho
+        __shared__ double esh[kIso ? 2 : 1][BX];          // isothermal: F_{d/2}(nu) per eigen-channel
         __shared__ C omsh[kPos ? BX : 1];                 // per-cell relaxation rate
         C (*qs)[BX] = reinterpret_cast<C (*)[BX]>(lds);
         C a[Q];
@@ -232,8 +233,21 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
 #pragma unroll
                     for (int i = 0; i < Q; ++i) ab[k - 1][i][lx] = a[i];
                 }
+            } else {
+                rsh[3][lx] = rk;
             }
             __syncthreads();
+            if constexpr (kIso) {
+                // isothermal model: the Fermi-Dirac state at beta = beta0 with the
+                // cell's density matrix; its eigen-channels (tr rho +- |rho|)/2 are
+                // inverted by waves 1 (up) and 2 (down) side by side
+                if (k == 1 || k == 2) {
+                    const double rv = sqrt(rsh[0][lx] * rsh[0][lx] + rsh[1][lx] * rsh[1][lx] + rsh[2][lx] * rsh[2][lx]);
+                    const double n = 0.5 * (rsh[3][lx] + (k == 1 ? rv : -rv));
+                    esh[k - 1][lx] = fd::iso_channel<D>(p.beta0, n, fp);
+                }
+                __syncthreads();
+            }
         }
         if (k == 0) {
             // moments (Eq. DiscrAvr) in double; sums over c_i in {0, +-1}
@@ -251,13 +265,8 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
             const double uu = u0 * u0 + u1 * u1 + u2 * u2;
             double eps = p.half_xi2 * K * invT - 0.5 * uu;
             if constexpr (kIso) {
-                // isothermal model: the Fermi-Dirac state at beta = beta0 with the
-                // cell's density matrix, eigenvalues (tr rho +- |rho|)/2
                 const double rv = sqrt(rsh[0][lx] * rsh[0][lx] + rsh[1][lx] * rsh[1][lx] + rsh[2][lx] * rsh[2][lx]);
-                double nu_up = 0.0, nu_dn = 0.0;
-                fd::channel_nu<D>(0.5 * (rk + rv), p.beta0, nu_up);
-                fd::channel_nu<D>(0.5 * (rk - rv), p.beta0, nu_dn);
-                eps = fd::internal_energy<D>(p.beta0, nu_up, nu_dn, fp);
+                eps = fd::iso_energy<D>(p.beta0, 0.5 * (rk + rv), 0.5 * (rk - rv), esh[0][lx], esh[1][lx]);
             }
             // polynomial factor (Eq. WeqAlgo, Appendix), with v = beta0 xi u so that
             // beta0 e_i.u = c_i.v:
