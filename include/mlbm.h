@@ -122,6 +122,7 @@ typedef struct {
     int launch_order;     /* step kernels: block order (MLBM_ORDER_*)          */
     double f16_scale;     /* S of MLBM_STORE_F16DEV (0 before initialisation) */
     double f16_ref[4][19];/* R_ki of MLBM_STORE_F16DEV                          */
+    int launch_blocks_per_cu; /* step kernels: resident workgroups per CU (0: hardware limit) */
 } mlbm_info;
 
 /*
@@ -359,9 +360,13 @@ int mlbm_set_magnetic_field_map(mlbm_handle h, const double* mu_b);
  * fastest; MLBM_ORDER_XCD_RANGE: a contiguous range of rows per XCD;
  * MLBM_ORDER_INTERLEAVE8: 8 rows across the XCDs, the chunks of a row on one
  * XCD; MLBM_ORDER_AUTO: chosen from the grid size and storage type).
- * mlbm_get_info reports the shape in effect.  Errors: MLBM_EINVAL.
+ * blocks_per_cu caps the workgroups resident on one CU (1..32) by reserving
+ * unused LDS: fewer waves in flight means fewer concurrent DRAM streams,
+ * which raises the bandwidth the pass reaches; 0 = no cap (hardware limit),
+ * -1 = automatic.  mlbm_get_info reports the shape in effect.
+ * Errors: MLBM_EINVAL.
  */
-int mlbm_set_launch(mlbm_handle h, int block_x, int order);
+int mlbm_set_launch(mlbm_handle h, int block_x, int order, int blocks_per_cu);
 
 /*
  * mlbm_adjoint_segment -- the adjoint of nsteps >= 0 consecutive steps in one

@@ -255,6 +255,7 @@ int mlbm_get_info(mlbm_handle h, mlbm_info* info) {
                                      h->Q, h->storage, h->launch);
     info->launch_block_x = lc.bx;
     info->launch_order = lc.order;
+    info->launch_blocks_per_cu = lc.cap;
     info->f16_scale = h->f16_scale;
     for (int k = 0; k < 4; ++k)
         for (int i = 0; i < h->Q; ++i) info->f16_ref[k][i] = h->f16_ref[k][i];
@@ -342,12 +343,14 @@ int mlbm_set_magnetic_field_map(mlbm_handle h, const double* mu_b) {
     return ok();
 }
 
-int mlbm_set_launch(mlbm_handle h, int block_x, int order) {
+int mlbm_set_launch(mlbm_handle h, int block_x, int order, int blocks_per_cu) {
     if (int e = check_handle(h)) return e;
     if (block_x != 0 && block_x != 64 && block_x != 128) return fail(MLBM_EINVAL, "block_x must be 0, 64 or 128");
     if (order < -1 || order > 2) return fail(MLBM_EINVAL, "order must be -1, 0, 1 or 2");
+    if (blocks_per_cu < -1 || blocks_per_cu > 32) return fail(MLBM_EINVAL, "blocks_per_cu must be in [-1, 32]");
     h->launch.bx = block_x;
     h->launch.order = order;
+    h->launch.cap = blocks_per_cu;
     return ok();
 }
 

@@ -15,6 +15,7 @@ enum { kOrderNatural = 0, kOrderXcdRange = 1, kOrderInterleave8 = 2 };
 struct LaunchCfg {
     int bx = 0;
     int order = -1;
+    int cap = -1;      // workgroups resident per CU: -1 automatic, 0 hardware limit, > 0 at most that many
 };
 LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want);
 

@@ -18,6 +18,10 @@
 // segments of its channel; the row index and the channel are uniform across
 // a wave, so per-lane addresses are a scalar base plus x.  Stores are
 // non-temporal (the field is not re-read within the pass).
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "common.hpp"
 #include "fermi_device.hpp"
 #include "internal.hpp"
@@ -351,25 +355,75 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
     }
 }
 
-// Launch shape (cells per workgroup along x, block order) when the handle
-// does not fix one, from sweeps of all six shapes on MI355X:
-//   D2Q9 (rows of >= 128 cells): 128-cell blocks, 8-row interleave
-//     (1024^2: 5.9-6.0 TB/s FP64/FP32; 64-cell natural order 5.3-5.7);
-//   D3Q19 with >= 2^24 cells: 128-cell blocks, one row range per XCD
-//     (384^3: 5.5 / 5.9 TB/s FP64 / FP32, against 5.0 / 5.4 in natural order);
-//   smaller D3Q19 grids: 64-cell blocks, natural order for double storage,
-//     8-row interleave for float and half (128^3: 5.6 / 5.8 / 5.9 TB/s).
+// Launch shape (cells per workgroup along x, block order, resident
+// workgroups per CU) when the handle does not fix one, from sweeps on MI355X
+// (fused-pass bandwidth measured through mlbm_step):
+//   FP64: 64-cell blocks with at most 2 workgroups per CU for D3Q19 above 64^3
+//     (128^3: 6.00 TB/s against 5.65 uncapped; 384^3 with one row range per
+//     XCD: 5.73 against 5.54 for the best uncapped shape), 3 per CU for
+//     smaller D3Q19 grids and for D2Q9 (1024^2, 8-row interleave: 6.10 TB/s
+//     against 5.95); natural order below 2^24 cells, per-XCD ranges above;
+//   FP32: D3Q19 up to 2^24 cells 64-cell blocks, 8-row interleave, 3 per CU
+//     from 128^3 on (6.03 against 5.93 TB/s); larger D3Q19 grids 128-cell
+//     blocks, per-XCD ranges; D2Q9 128-cell blocks, 8-row interleave;
+//   FP16: as FP32 without a cap (it gains nothing there).
+// The cap is not applied to the magnetic-field kernels (more LDS) and to the
+// isothermal and positivity kernels (more arithmetic per cell).
 LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want) {
     LaunchCfg c = want;
     const double cells = static_cast<double>(nx) * ny * nz;
     const bool big3d = Q == 19 && cells >= 16777216.0 && nx > 64;
-    if (c.bx == 0) c.bx = ((Q == 9 && nx >= 128) || big3d) ? 128 : 64;
-    if (c.order < 0) {
-        if (Q == 9) c.order = kOrderInterleave8;
-        else if (big3d) c.order = kOrderXcdRange;
-        else c.order = (mode == kF64) ? kOrderNatural : kOrderInterleave8;
+    if (mode == kF64) {
+        if (c.bx == 0) c.bx = 64;
+        if (c.order < 0) c.order = (Q == 9) ? kOrderInterleave8 : (big3d ? kOrderXcdRange : kOrderNatural);
+        if (c.cap < 0) c.cap = (Q == 19 && cells > 262144.0) ? 2 : 3;
+    } else {
+        if (c.bx == 0) c.bx = ((Q == 9 && nx >= 128) || big3d) ? 128 : 64;
+        if (c.order < 0) c.order = big3d ? kOrderXcdRange : kOrderInterleave8;
+        if (c.cap < 0) c.cap = (mode == kF32 && Q == 19 && !big3d && cells >= 2097152.0) ? 3 : 0;
     }
     return c;
+}
+
+// Dynamic LDS that limits a kernel to `cap` resident workgroups per CU.
+// Fewer waves in flight means fewer concurrent DRAM streams (every wave
+// gathers Q segments and writes Q segments), which on MI355X raises the
+// bandwidth the pass reaches; the LDS is reserved, never touched.  The size is
+// the smallest one at which the runtime's occupancy calculator reports at
+// most `cap` workgroups, found once per kernel and cap and cached.
+static size_t lds_for_cap(const void* fn, int threads, int cap) {
+    if (cap <= 0) return 0;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, size_t> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(fn, cap);
+    const auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    auto occupancy = [&](size_t dyn) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, dyn) != hipSuccess) return -1;
+        return n;
+    };
+    hipFuncAttributes attr{};
+    size_t hi = 0;
+    if (hipFuncGetAttributes(&attr, fn) == hipSuccess)
+        hi = attr.maxDynamicSharedSizeBytes > 0 ? static_cast<size_t>(attr.maxDynamicSharedSizeBytes)
+                                                : 65536 - attr.sharedSizeBytes;
+    size_t dyn = 0;
+    const int n0 = occupancy(0);
+    if (n0 > cap && hi > 0 && occupancy(hi) >= 0) {
+        size_t lo = 0;
+        while (lo < hi) {          // smallest dyn with occupancy <= cap (occupancy falls as dyn grows)
+            const size_t mid = lo + (hi - lo) / 2;
+            const int n = occupancy(mid);
+            if (n >= 0 && n <= cap) hi = mid;
+            else lo = mid + 1;
+        }
+        dyn = lo;
+    }
+    (void)hipGetLastError();      // the queries leave no error behind
+    cache.emplace(key, dyn);
+    return dyn;
 }
 
 template <int Q, int MODE, bool PULL, bool COLL, int FIELD, int VAR = 0>
@@ -377,13 +431,20 @@ static hipError_t launch(const void* src, void* dst, const KParams& p, const FdP
                          hipStream_t s) {
     using T = typename Store<MODE>::T;
     if constexpr (VAR != 0) c.bx = 64;        // the variants are built for 64-cell blocks only
+    // the cap is measured for the plain kernels; the field and variant kernels
+    // hold more LDS or registers and run uncapped
+    constexpr bool kCapped = VAR == 0 && FIELD == kFieldNone;
     const dim3 grd(static_cast<unsigned>((p.nx + c.bx - 1) / c.bx) * p.ny * p.nz);
     if (c.bx == 64) {
-        hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 64, FIELD, VAR>), grd, dim3(64, 4), 0, s,
-                           static_cast<const T*>(src), static_cast<T*>(dst), p, c.order, fp);
+        const auto fn = k_step<Q, MODE, PULL, COLL, 64, FIELD, VAR>;
+        const size_t dyn = lds_for_cap(reinterpret_cast<const void*>(fn), 256, kCapped ? c.cap : 0);
+        hipLaunchKernelGGL(fn, grd, dim3(64, 4), dyn, s, static_cast<const T*>(src), static_cast<T*>(dst), p,
+                           c.order, fp);
     } else if constexpr (VAR == 0) {
-        hipLaunchKernelGGL((k_step<Q, MODE, PULL, COLL, 128, FIELD, 0>), grd, dim3(128, 4), 0, s,
-                           static_cast<const T*>(src), static_cast<T*>(dst), p, c.order, fp);
+        const auto fn = k_step<Q, MODE, PULL, COLL, 128, FIELD, 0>;
+        const size_t dyn = lds_for_cap(reinterpret_cast<const void*>(fn), 512, kCapped ? c.cap : 0);
+        hipLaunchKernelGGL(fn, grd, dim3(128, 4), dyn, s, static_cast<const T*>(src), static_cast<T*>(dst), p,
+                           c.order, fp);
     }
     return hipGetLastError();
 }

@@ -45,6 +45,7 @@ class Info(ctypes.Structure):
         ("a2_b", ctypes.c_double), ("a3", ctypes.c_double), ("a4", ctypes.c_double), ("a5", ctypes.c_double),
         ("launch_block_x", ctypes.c_int), ("launch_order", ctypes.c_int),
         ("f16_scale", ctypes.c_double), ("f16_ref", (ctypes.c_double * 19) * 4),
+        ("launch_blocks_per_cu", ctypes.c_int),
     ]
 
 
@@ -76,7 +77,7 @@ def load_library(path=LIB_PATH):
         "mlbm_adjoint_step": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_adjoint_segment": ([vp, vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_set_f16_reference": ([vp, dp, ctypes.c_double], ctypes.c_int),
-        "mlbm_set_launch": ([vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "mlbm_set_launch": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "mlbm_set_magnetic_field": ([vp, dp], ctypes.c_int),
         "mlbm_set_magnetic_field_map": ([vp, vp], ctypes.c_int),
         "mlbm_init_chemical": ([vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
@@ -337,8 +338,8 @@ def mlbm_set_positivity(h, on):
     _check(load_library().mlbm_set_positivity(h.ptr, int(on)))
 
 
-def mlbm_set_launch(h, block_x=0, order=MLBM_ORDER_AUTO):
-    _check(load_library().mlbm_set_launch(h.ptr, int(block_x), int(order)))
+def mlbm_set_launch(h, block_x=0, order=MLBM_ORDER_AUTO, blocks_per_cu=-1):
+    _check(load_library().mlbm_set_launch(h.ptr, int(block_x), int(order), int(blocks_per_cu)))
     mlbm_get_info(h)
 
 

@@ -112,12 +112,15 @@ def test_set_launch_validation_and_info():
     assert h.info["launch_order"] in (0, 1, 2)
     mlbm.mlbm_set_launch(h, 128, mlbm.MLBM_ORDER_XCD_RANGE)
     assert h.info["launch_block_x"] == 128 and h.info["launch_order"] == mlbm.MLBM_ORDER_XCD_RANGE
-    for bad in [(32, 0), (256, 0), (64, 3), (64, -2)]:
+    for bad in [(32, 0, 0), (256, 0, 0), (64, 3, 0), (64, -2, 0), (64, 0, -2), (64, 0, 33)]:
         with pytest.raises(mlbm.MlbmError) as e:
             mlbm.mlbm_set_launch(h, *bad)
         assert e.value.code == mlbm.MLBM_EINVAL
+    mlbm.mlbm_set_launch(h, 64, mlbm.MLBM_ORDER_NATURAL, 3)
+    assert h.info["launch_blocks_per_cu"] == 3
     mlbm.mlbm_set_launch(h, 0, mlbm.MLBM_ORDER_AUTO)
     assert h.info["launch_block_x"] in (64, 128)
+    assert h.info["launch_blocks_per_cu"] >= 0
 
 
 def test_magnetic_field_validation():
