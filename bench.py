@@ -111,7 +111,10 @@ def measure_step(shape, seed, tau, storage, steps, warmup, f, field=None, isothe
     bytes_per_cell = 2 * 4 * Q * {0: 8, 1: 4, 2: 2}[storage] + extra_bytes
     achieved = bytes_per_cell * N / (fused_ms * 1e-3) / 1e9
     drift = float(np.max(np.abs(g1 - g0)) / np.max(np.abs(g0)))
+    info = h.info
     out = {
+        "launch": {"block_x": info["launch_block_x"], "order": ["natural", "xcd_range", "interleave8"][info["launch_order"]],
+                   "blocks_per_cu": info["launch_blocks_per_cu"]},
         "mlups": N * steps / (t_all * 1e-3) / 1e6,
         "ms_per_step": t_all / steps,
         "fused_kernel_ms": fused_ms,
@@ -321,6 +324,7 @@ def main():
                      "traffic": measured_traffic() if args.workload == "d3q19_128" else None,
                      "algorithmic_bytes_per_launch": r64["bytes_per_cell"] * int(np.prod(shape)),
                      "kernel": "k_step<19, F64, pull, collide>", "kernel_ms": r64["fused_kernel_ms"],
+                     "launch": r64["launch"],
                      "bytes_per_cell": r64["bytes_per_cell"]},
         "f64": r64,
     }
