@@ -33,7 +33,8 @@ __device__ __forceinline__ void push_coords(int x, int n, int stride, int out[3]
 template <int Q, int MODE, bool WPULL>
 __global__ void __launch_bounds__(256)
 k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<MODE>::T* __restrict__ ln1,
-          typename Store<MODE>::T* __restrict__ ln, const KParams p, double* __restrict__ partials) {
+          typename Store<MODE>::T* __restrict__ ln, const KParams p, double* __restrict__ partials,
+          const int accumulate) {
     using T = typename Store<MODE>::T;
     constexpr int D = Lat<Q>::D;
     __shared__ double sh[256];
@@ -162,7 +163,7 @@ k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<M
     }
     if (tid == 0) {
         const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        partials[bid] = sh[0];
+        partials[bid] = accumulate ? partials[bid] + sh[0] : sh[0];
     }
 }
 
@@ -178,25 +179,25 @@ int adjoint_blocks(int nx, int ny, int nz) {
 
 template <int Q, int MODE>
 static hipError_t adj_q(bool wpull, const void* Wn, const void* l1, void* l0, const KParams& p, double* partials,
-                        hipStream_t s) {
+                        bool accumulate, hipStream_t s) {
     using T = typename Store<MODE>::T;
     dim3 blk = adj_block(p.nx);
     dim3 grd((p.nx + blk.x - 1) / blk.x, (p.ny + blk.y - 1) / blk.y, p.nz);
     if (wpull)
         hipLaunchKernelGGL((k_adjoint<Q, MODE, true>), grd, blk, 0, s, static_cast<const T*>(Wn),
-                           static_cast<const T*>(l1), static_cast<T*>(l0), p, partials);
+                           static_cast<const T*>(l1), static_cast<T*>(l0), p, partials, accumulate ? 1 : 0);
     else
         hipLaunchKernelGGL((k_adjoint<Q, MODE, false>), grd, blk, 0, s, static_cast<const T*>(Wn),
-                           static_cast<const T*>(l1), static_cast<T*>(l0), p, partials);
+                           static_cast<const T*>(l1), static_cast<T*>(l0), p, partials, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint(int Q, int mode, bool wpull, const void* Wn, const void* lam_next, void* lam_n,
-                          const KParams& p, double* partials, hipStream_t s) {
-    if (Q == 9) return mode == kF64 ? adj_q<9, kF64>(wpull, Wn, lam_next, lam_n, p, partials, s)
-                                    : adj_q<9, kF32>(wpull, Wn, lam_next, lam_n, p, partials, s);
-    return mode == kF64 ? adj_q<19, kF64>(wpull, Wn, lam_next, lam_n, p, partials, s)
-                        : adj_q<19, kF32>(wpull, Wn, lam_next, lam_n, p, partials, s);
+                          const KParams& p, double* partials, bool accumulate, hipStream_t s) {
+    if (Q == 9) return mode == kF64 ? adj_q<9, kF64>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, s)
+                                    : adj_q<9, kF32>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, s);
+    return mode == kF64 ? adj_q<19, kF64>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, s)
+                        : adj_q<19, kF32>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, s);
 }
 
 }  // namespace mlbm

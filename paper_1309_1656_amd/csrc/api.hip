@@ -543,7 +543,7 @@ int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next, void
     if (int e = ensure_scratch(h, std::max<size_t>(static_cast<size_t>(nb), static_cast<size_t>(kRedBlocks) * kRedSlots)))
         return e;
     hipStream_t s = as_stream(stream);
-    HIP_TRY(launch_adjoint(h->Q, h->storage, false, W_n, lam_next, lam_n, h->kp, h->d_partials, s));
+    HIP_TRY(launch_adjoint(h->Q, h->storage, false, W_n, lam_next, lam_n, h->kp, h->d_partials, false, s));
     if (dL_domega) HIP_TRY(launch_finalize(h->d_partials, nb, 1, 0u, nullptr, dL_domega, 1.0, s));
     return ok();
 }
@@ -576,12 +576,13 @@ int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps,
     for (int j = nsteps - 1; j >= 0; --j) {
         const bool pulled = j > 0;
         const void* wsrc = pulled ? static_cast<const void*>(st + (j - 1) * fb) : W;
-        HIP_TRY(launch_adjoint(h->Q, h->storage, pulled, wsrc, in, out, h->kp, h->d_partials, s));
-        if (dL_domega) HIP_TRY(launch_finalize(h->d_partials, nb, 1, 0u, nullptr, dL_domega, 1.0, s));
+        // block partials of dL/domega accumulate over the segment: one final sum
+        HIP_TRY(launch_adjoint(h->Q, h->storage, pulled, wsrc, in, out, h->kp, h->d_partials, j < nsteps - 1, s));
         void* t = in;
         in = out;
         out = t;
     }
+    if (dL_domega) HIP_TRY(launch_finalize(h->d_partials, nb, 1, 0u, nullptr, dL_domega, 1.0, s));
     if (in != lam) HIP_TRY(hipMemcpyAsync(lam, in, fb, hipMemcpyDeviceToDevice, s));
     return ok();
 }

@@ -50,7 +50,7 @@ hipError_t launch_spin_loss(int Q, int mode, const void* W, const double* r_targ
 // (adjoint_blocks(nx, ny, nz) values, stride 1).  With wpull, Wn is the
 // previous post-collision state and W_n is gathered from it by a pull.
 hipError_t launch_adjoint(int Q, int mode, bool wpull, const void* Wn, const void* lam_next, void* lam_n,
-                          const KParams& p, double* partials, hipStream_t s);
+                          const KParams& p, double* partials, bool accumulate, hipStream_t s);
 
 // Initial Fermi-Dirac state.  phase 0: only reduce global sums (slots 0..3
 // rho_k, 4..6 tr(rho) u, 7 total energy); phase 1: reduce max |a - R| / w_i

@@ -145,4 +145,6 @@ def test_adjoint_segment_equals_stepwise(shape, n):
     dom_b = torch.zeros(1, dtype=torch.float64, device="cuda")
     mlbm.mlbm_adjoint_segment(h, W0, buf, n, lam_b, h.empty_field(), dom_b)
     assert torch.equal(lam, lam_b)
-    assert dom_a.item() == dom_b.item()
+    # the segment sums dL/domega per block over all steps before the one final
+    # sum, the stepwise calls per step: same terms, other rounding order
+    assert abs(dom_a.item() - dom_b.item()) <= 1e-13 * abs(dom_a.item())
