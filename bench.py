@@ -251,8 +251,20 @@ def cpu_baseline(seconds=12.0):
         n += 1
     dt = time.perf_counter() - t0
     return {"value": int(np.prod(shape)) * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"D3Q19 48^3 cells, {n} steps, tau 0.8, same initial-state family as the workload",
-            "host_cpus": os.cpu_count()}
+            "sample": f"D3Q19 48^3 cells, {n} steps, tau 0.8, same initial-state family as the workload; "
+                      "NumPy elementwise work, one thread",
+            "host_cpus": os.cpu_count(), "host_cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
