@@ -240,13 +240,18 @@ int mlbm_init_chemical(mlbm_handle h, void* W, const double* nu, const double* a
  * second field of the same size, distinct from W, clobbered.  Implementation:
  * one collide-only pass, nsteps - 1 fused pull-stream + collide passes, one
  * stream-only pass, ping-ponging between W and scratch so that no copy is made.
+ * The collision is the one configured on the handle (equilibrium mode,
+ * positivity limit, magnetic field).  Only kernel launches are enqueued (no
+ * allocation, memset or synchronisation), so the call can be captured in a
+ * HIP graph and replayed.
  * Errors: MLBM_EINVAL (null or equal pointers, nsteps < 0), MLBM_EHIP.
  */
 int mlbm_step(mlbm_handle h, void* W, void* scratch, int nsteps, void* stream);
 
 /*
  * mlbm_collide -- dst = C(src), the BGK collision of Eq. CollisionStep cell
- * by cell, no streaming.  dst may equal src (in place).
+ * by cell (as configured on the handle), no streaming.  dst may equal src
+ * (in place).
  */
 int mlbm_collide(mlbm_handle h, const void* src, void* dst, void* stream);
 
