@@ -342,8 +342,10 @@ int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next,
  * i.e. every Bloch vector turns by 2 Delta t |mu B| about B; it commutes with
  * the BGK collision of a cell, so the order of the two does not matter.
  * Traces (density, momentum, energy) are untouched; tr(rho sigma) precesses.
- * Needs MLBM_EQ_DIRECT without the positivity limit; not combinable with the
- * adjoint (MLBM_EINVAL).
+ * Needs MLBM_EQ_DIRECT without the positivity limit (MLBM_EINVAL).  The
+ * adjoint entry points follow the field: the Bloch part of the adjoint is
+ * turned back by the transpose of each cell's rotation before the
+ * collision's adjoint.
  */
 int mlbm_set_magnetic_field(mlbm_handle h, const double mu_b[3]);
 

@@ -44,9 +44,13 @@ def poly_factor_grad(lat, u, eps):
 
 def step_vjp(lat, W, Lam_next, tau, dt=1.0):
     """(Lam_n, dL/dw) for one step from the pre-collision state W = W_n."""
+    return collision_vjp(lat, W, stream(lat, Lam_next, sign=-1), tau, dt)
+
+
+def collision_vjp(lat, W, G, tau, dt=1.0):
+    """(Lam_n, dL/dw) of the collision alone, G being the adjoint of its output."""
     om = dt / tau
     g = W.ndim - 3
-    G = stream(lat, Lam_next, sign=-1)
     rho, T, u, eps = moments(lat, W)
     P = poly_factor(lat, u, eps)
     wP = _bshape(lat.w, g) * P

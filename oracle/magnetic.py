@@ -16,6 +16,7 @@ pin it against direct numerical integration of dW/dt = -i [mu sigma.B, W].
 import numpy as np
 from scipy.linalg import expm
 
+from . import adjoint
 from .pauli import SIGMA
 from .qlbm import collide, stream
 
@@ -48,3 +49,14 @@ def run_with_field(lat, W, tau, mu_b, nsteps):
     for _ in range(nsteps):
         W = step_with_field(lat, W, tau, mu_b)
     return W
+
+
+def step_vjp_with_field(lat, W, Lam_next, tau, mu_b, dt=1.0):
+    """(Lam_n, dL/dw) of one step with the field: W_{n+1} = S(P(C(W_n))) with
+    P(X) = U X U*.  Under the pairing Re tr(Lam X) the adjoint of P is
+    Y -> U* Y U, so the adjoint of the streamed output is turned back before
+    the collision's adjoint."""
+    G = stream(lat, Lam_next, sign=-1)
+    U = precession_unitary(mu_b, dt)
+    Uh = np.conj(np.swapaxes(U, -1, -2))
+    return adjoint.collision_vjp(lat, W, Uh[None] @ G @ U[None], tau, dt)

@@ -15,6 +15,9 @@
 // arithmetic is in double.  The trace channel is handled first and last so
 // that each Bloch channel k = 1..3 is loaded, used and written in turn.
 //
+// With a magnetic field (FIELD) the Bloch part of g is turned back by the
+// transpose of the cell's rotation before it enters the collision's adjoint.
+//
 // W_n can be read as stored (WPULL = false) or gathered from the previous
 // post-collision state S_{n-1}, W_n,i(x) = S_{n-1},i(x - c_i) (WPULL = true),
 // so that a recomputed segment needs one fused pass per state.
@@ -30,7 +33,7 @@ __device__ __forceinline__ void push_coords(int x, int n, int stride, int out[3]
     out[2] = ((x + 1 == n) ? 0 : x + 1) * stride;
 }
 
-template <int Q, int MODE, bool WPULL>
+template <int Q, int MODE, bool WPULL, int FIELD>
 __global__ void __launch_bounds__(256)
 k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<MODE>::T* __restrict__ ln1,
           typename Store<MODE>::T* __restrict__ ln, const KParams p, double* __restrict__ partials,
@@ -105,6 +108,30 @@ k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<M
             dom += g0[i] * (wP[i] * Tr - a0[i]);
             G[i] = p.w[i] * g0[i] * Tr;
         }
+        // With a magnetic field the collision output was turned by the Bloch
+        // rotation R of the cell (Sec. 5, Eq. sigmaB_comm) before streaming; its
+        // adjoint turns the Bloch part of g back: g'_l = sum_k R_kl g_k.
+        double gB[FIELD != kFieldNone ? 3 : 1][FIELD != kFieldNone ? Q : 1];
+        if constexpr (FIELD != kFieldNone) {
+            double R[9];
+            if constexpr (FIELD == kFieldUniform) {
+#pragma unroll
+                for (int j = 0; j < 9; ++j) R[j] = p.rot[j];
+            } else {
+                const size_t cell = row * nx + x;
+                const size_t N = static_cast<size_t>(p.ncell);
+                const double bm[3] = {p.bmap[cell], p.bmap[N + cell], p.bmap[2 * N + cell]};
+                rotation_matrix(bm, R);
+            }
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                double v[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) v[k] = static_cast<double>(ln1[fidx(Q, nx, srow[i], k + 1, i, sx[i])]);
+#pragma unroll
+                for (int l = 0; l < 3; ++l) gB[l][i] = R[l] * v[0] + R[3 + l] * v[1] + R[6 + l] * v[2];
+            }
+        }
         // Bloch channels
 #pragma unroll
         for (int k = 1; k < 4; ++k) {
@@ -118,7 +145,8 @@ k_adjoint(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<M
             double hk = 0.0;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                gk[i] = static_cast<double>(ln1[fidx(Q, nx, srow[i], k, i, sx[i])]);
+                if constexpr (FIELD != kFieldNone) gk[i] = gB[k - 1][i];
+                else gk[i] = static_cast<double>(ln1[fidx(Q, nx, srow[i], k, i, sx[i])]);
                 hk += gk[i] * wP[i];
                 dom += gk[i] * (wP[i] * rk - ak[i]);
                 G[i] += p.w[i] * gk[i] * rk;
@@ -177,19 +205,27 @@ int adjoint_blocks(int nx, int ny, int nz) {
     return ((nx + blk.x - 1) / blk.x) * ((ny + blk.y - 1) / blk.y) * nz;
 }
 
-template <int Q, int MODE>
-static hipError_t adj_q(bool wpull, const void* Wn, const void* l1, void* l0, const KParams& p, double* partials,
+template <int Q, int MODE, int FIELD>
+static hipError_t adj_f(bool wpull, const void* Wn, const void* l1, void* l0, const KParams& p, double* partials,
                         bool accumulate, hipStream_t s) {
     using T = typename Store<MODE>::T;
     dim3 blk = adj_block(p.nx);
     dim3 grd((p.nx + blk.x - 1) / blk.x, (p.ny + blk.y - 1) / blk.y, p.nz);
     if (wpull)
-        hipLaunchKernelGGL((k_adjoint<Q, MODE, true>), grd, blk, 0, s, static_cast<const T*>(Wn),
+        hipLaunchKernelGGL((k_adjoint<Q, MODE, true, FIELD>), grd, blk, 0, s, static_cast<const T*>(Wn),
                            static_cast<const T*>(l1), static_cast<T*>(l0), p, partials, accumulate ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_adjoint<Q, MODE, false>), grd, blk, 0, s, static_cast<const T*>(Wn),
+        hipLaunchKernelGGL((k_adjoint<Q, MODE, false, FIELD>), grd, blk, 0, s, static_cast<const T*>(Wn),
                            static_cast<const T*>(l1), static_cast<T*>(l0), p, partials, accumulate ? 1 : 0);
     return hipGetLastError();
+}
+
+template <int Q, int MODE>
+static hipError_t adj_q(bool wpull, const void* Wn, const void* l1, void* l0, const KParams& p, double* partials,
+                        bool accumulate, hipStream_t s) {
+    if (p.field_mode == kFieldUniform) return adj_f<Q, MODE, kFieldUniform>(wpull, Wn, l1, l0, p, partials, accumulate, s);
+    if (p.field_mode == kFieldMap) return adj_f<Q, MODE, kFieldMap>(wpull, Wn, l1, l0, p, partials, accumulate, s);
+    return adj_f<Q, MODE, kFieldNone>(wpull, Wn, l1, l0, p, partials, accumulate, s);
 }
 
 hipError_t launch_adjoint(int Q, int mode, bool wpull, const void* Wn, const void* lam_next, void* lam_n,

@@ -537,7 +537,6 @@ int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next, void
     if (h->storage == MLBM_STORE_F16DEV) return fail(MLBM_EINVAL, "the adjoint needs F64 or F32 storage");
     if (h->eq_mode != MLBM_EQ_DIRECT || h->positivity)
         return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode without the positivity limit");
-    if (h->kp.field_mode != kFieldNone) return fail(MLBM_EINVAL, "the adjoint does not take a magnetic field");
     if (lam_n == W_n || lam_n == lam_next) return fail(MLBM_EINVAL, "lam_n must not alias the inputs");
     const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));
     if (int e = ensure_scratch(h, std::max<size_t>(static_cast<size_t>(nb), static_cast<size_t>(kRedBlocks) * kRedSlots)))
@@ -556,7 +555,6 @@ int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps,
     if (h->storage == MLBM_STORE_F16DEV) return fail(MLBM_EINVAL, "the adjoint needs F64 or F32 storage");
     if (h->eq_mode != MLBM_EQ_DIRECT || h->positivity)
         return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode without the positivity limit");
-    if (h->kp.field_mode != kFieldNone) return fail(MLBM_EINVAL, "the adjoint does not take a magnetic field");
     if (lam == lam_tmp || lam == W || lam_tmp == W) return fail(MLBM_EINVAL, "lam, lam_tmp and W must be distinct");
     if (nsteps == 0) return ok();
     const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));

@@ -137,4 +137,32 @@ constexpr int kRedSlots = 10;
 constexpr int kRedBlocks = 1024;
 constexpr int kRedThreads = 256;
 
+// Row k of the rotation of the Bloch vector produced by the magnetic-field
+// commutator -i [mu sigma.B, W] over one time step (Sec. 5, Eq. sigmaB_comm):
+// W -> U W U*, U = exp(-i Delta t sigma.(mu B)), turns every Bloch vector by
+// theta = 2 Delta t |mu B| about the unit axis n of B (Rodrigues):
+//   R = cos(theta) I + sin(theta) [n]x + (1 - cos(theta)) n n^T.
+__device__ __forceinline__ void rotation_row(const double b[3], int k, double r[3]) {
+    const double bb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    if (bb == 0.0) {
+        r[0] = (k == 0) ? 1.0 : 0.0;
+        r[1] = (k == 1) ? 1.0 : 0.0;
+        r[2] = (k == 2) ? 1.0 : 0.0;
+        return;
+    }
+    double sn, cs;
+    sincos(2.0 * bb, &sn, &cs);
+    const double n[3] = {b[0] / bb, b[1] / bb, b[2] / bb};
+    // [n]x row k: (0, -n2, n1), (n2, 0, -n0), (-n1, n0, 0)
+    const double cx[3][3] = {{0.0, -n[2], n[1]}, {n[2], 0.0, -n[0]}, {-n[1], n[0], 0.0}};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) r[l] = ((k == l) ? cs : 0.0) + sn * cx[k][l] + (1.0 - cs) * n[k] * n[l];
+}
+
+// The whole rotation: R[3 * k + l], Bloch components k, l = 0..2 (x, y, z).
+__device__ __forceinline__ void rotation_matrix(const double b[3], double R[9]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rotation_row(b, k, R + 3 * k);
+}
+
 }  // namespace mlbm

@@ -142,28 +142,6 @@ __device__ __forceinline__ C psd_bound(C a0, C a1, C a2, C a3, C e0, C e1, C e2,
     return best < C(0) ? C(0) : best;
 }
 
-// Row k of the rotation of the Bloch vector produced by the magnetic-field
-// commutator -i [mu sigma.B, W] over one time step (Sec. 5, Eq. sigmaB_comm):
-// W -> U W U*, U = exp(-i Delta t sigma.(mu B)), turns every Bloch vector by
-// theta = 2 Delta t |mu B| about the unit axis n of B (Rodrigues):
-//   R = cos(theta) I + sin(theta) [n]x + (1 - cos(theta)) n n^T.
-__device__ __forceinline__ void rotation_row(const double b[3], int k, double r[3]) {
-    const double bb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-    if (bb == 0.0) {
-        r[0] = (k == 0) ? 1.0 : 0.0;
-        r[1] = (k == 1) ? 1.0 : 0.0;
-        r[2] = (k == 2) ? 1.0 : 0.0;
-        return;
-    }
-    double sn, cs;
-    sincos(2.0 * bb, &sn, &cs);
-    const double n[3] = {b[0] / bb, b[1] / bb, b[2] / bb};
-    // [n]x row k: (0, -n2, n1), (n2, 0, -n0), (-n1, n0, 0)
-    const double cx[3][3] = {{0.0, -n[2], n[1]}, {n[2], 0.0, -n[0]}, {-n[1], n[0], 0.0}};
-#pragma unroll
-    for (int l = 0; l < 3; ++l) r[l] = ((k == l) ? cs : 0.0) + sn * cx[k][l] + (1.0 - cs) * n[k] * n[l];
-}
-
 template <int Q, int MODE, bool PULL, bool COLL, int BX, int FIELD, int VAR>
 __global__ void __launch_bounds__(BX * 4)
 k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T* __restrict__ dst,

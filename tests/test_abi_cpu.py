@@ -132,8 +132,8 @@ def test_magnetic_field_validation():
         mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_EIGEN)
     assert e.value.code == mlbm.MLBM_EINVAL
     buf = [ctypes.c_void_p(4096 * (j + 1)) for j in range(3)]
-    assert lib.mlbm_adjoint_step(h.ptr, buf[0], buf[1], buf[2], None, None) == mlbm.MLBM_EINVAL
-    assert "magnetic" in mlbm.mlbm_last_error()
+    # (the adjoint takes the field; only aliasing is checked here, which fails before any launch)
+    assert lib.mlbm_adjoint_step(h.ptr, buf[0], buf[1], buf[1], None, None) == mlbm.MLBM_EINVAL
     with pytest.raises(mlbm.MlbmError):
         mlbm.mlbm_set_magnetic_field(h, [float("nan"), 0.0, 0.0])
     # switched off (None or zero): both are allowed again
@@ -145,7 +145,6 @@ def test_magnetic_field_validation():
     assert lib.mlbm_set_magnetic_field_map(h.ptr, ctypes.c_void_p(4096)) == mlbm.MLBM_EINVAL
     mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_DIRECT)
     assert lib.mlbm_set_magnetic_field_map(h.ptr, ctypes.c_void_p(4096)) == mlbm.MLBM_OK
-    assert lib.mlbm_adjoint_step(h.ptr, buf[0], buf[1], buf[2], None, None) == mlbm.MLBM_EINVAL
     mlbm.mlbm_set_magnetic_field(h, None)
     assert lib.mlbm_set_magnetic_field(None, None) == mlbm.MLBM_EINVAL
 

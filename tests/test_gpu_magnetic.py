@@ -142,3 +142,61 @@ def test_field_map_update_between_steps():
     torch.cuda.synchronize()
     ref = magnetic.run_with_field(lat, magnetic.run_with_field(lat, Wo, 0.8, m1, 2), 0.8, m2, 3)
     assert normwise_rel_err(to_pauli_np(h, W), oracle_pauli(ref)) < 1e-12
+
+
+# ---- the adjoint with a field ---------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(37, 70), (13, 9, 11)])
+@pytest.mark.parametrize("uniform", [True, False])
+def test_field_adjoint_step_matches_oracle(shape, uniform):
+    _flush(f"field adjoint step {shape} uniform={uniform}")
+    lat, Wo = _state(shape, 13)
+    field, mu_b = _mu_b(shape, 5, uniform)
+    rng = np.random.default_rng(4)
+    lam1 = rng.standard_normal((4, lat.Q) + tuple(shape))
+    h = make_handle(shape, tau=0.7)
+    keep = None
+    if uniform:
+        mlbm.mlbm_set_magnetic_field(h, field)
+    else:
+        keep = torch.from_numpy(np.ascontiguousarray(field)).cuda()
+        mlbm.mlbm_set_magnetic_field_map(h, keep)
+    lam0 = h.empty_field()
+    dom = torch.zeros(1, dtype=torch.float64, device="cuda")
+    mlbm.mlbm_adjoint_step(h, from_pauli(h, oracle_pauli(Wo)), from_pauli(h, lam1), lam0, dom)
+    torch.cuda.synchronize()
+    L0, dom_o = magnetic.step_vjp_with_field(lat, Wo, pauli.matrix_from_pauli(2.0 * lam1), 0.7, mu_b)
+    assert normwise_rel_err(to_pauli_np(h, lam0), pauli.pauli_from_matrix(L0) / 2.0) < 1e-12
+    assert abs(dom.item() - dom_o) <= 1e-11 * abs(dom_o)
+
+
+@pytest.mark.parametrize("K", [3, 10])
+def test_field_rollout_gradient_matches_oracle(K):
+    from oracle import adjoint
+    from paper_1309_1656_amd import synthetic
+    from paper_1309_1656_amd.rollout import MLBMRollout
+    shape, tau, steps = (16, 16), 0.8, 10
+    _flush(f"field rollout K={K}")
+    f = fields(shape, synthetic.BASE_SEED + 5)
+    rt_np = synthetic.target_bloch_field(shape, synthetic.BASE_SEED + 105)
+    mu_b = np.random.default_rng(8).normal(0, 0.2, size=(3,) + shape)
+    h = make_handle(shape, tau=tau)
+    bmap = torch.from_numpy(mu_b).cuda()
+    mlbm.mlbm_set_magnetic_field_map(h, bmap)
+    W0 = gpu_init(h, f).requires_grad_(True)
+    tau_t = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+    loss = MLBMRollout.apply(W0, tau_t, h, steps, K, torch.from_numpy(rt_np).cuda())
+    loss.backward()
+    # oracle: every state stored, adjoint with the field
+    lat, Wo = oracle_init(shape, f)
+    states = [Wo]
+    for _ in range(steps):
+        states.append(magnetic.step_with_field(lat, states[-1], tau, mu_b))
+    Lo, Lam = adjoint.spin_loss(lat, states[-1], rt_np)
+    dom = 0.0
+    for n in range(steps - 1, -1, -1):
+        Lam, d = magnetic.step_vjp_with_field(lat, states[n], Lam, tau, mu_b)
+        dom += d
+    assert abs(loss.item() / Lo - 1) < 1e-12
+    assert normwise_rel_err(to_pauli_np(h, W0.grad), pauli.pauli_from_matrix(Lam) / 2.0) < 1e-11
+    assert abs(tau_t.grad.item() / (-dom / tau ** 2) - 1) < 1e-11

@@ -113,3 +113,30 @@ def test_joint_su2_covariance(d, shape):
     lhs = magnetic.run_with_field(lat, rot(W), 0.75, mu_b_rot, 3)
     rhs = rot(magnetic.run_with_field(lat, W, 0.75, mu_b, 3))
     assert np.max(np.abs(lhs - rhs)) < 1e-14
+
+
+@pytest.mark.parametrize("d,shape", [(2, (5, 6)), (3, (3, 4, 5))])
+def test_field_step_vjp_matches_finite_differences(d, shape):
+    lat, W = _state(d, shape, seed=9)
+    rng = np.random.default_rng(5)
+    mu_b = rng.normal(0, 0.3, size=(3,) + shape)
+    tau = 0.7
+    Lam_next = pauli.matrix_from_pauli(rng.normal(0, 1, size=(4, lat.Q) + shape))
+    Lam, dom = magnetic.step_vjp_with_field(lat, W, Lam_next, tau, mu_b)
+    pair = lambda A, B: float(np.real((A * np.swapaxes(B, -1, -2)).sum()))
+    for seed in (1, 2):
+        dW = pauli.matrix_from_pauli(np.random.default_rng(seed).normal(0, 1e-2, size=(4, lat.Q) + shape))
+        h = 1e-5
+        fd = (pair(Lam_next, magnetic.step_with_field(lat, W + h * dW, tau, mu_b))
+              - pair(Lam_next, magnetic.step_with_field(lat, W - h * dW, tau, mu_b))) / (2 * h)
+        assert abs(pair(Lam, dW) - fd) <= 1e-8 * max(1.0, abs(fd))
+    h = 1e-6
+    om = 1.0 / tau
+    fd = (pair(Lam_next, magnetic.step_with_field(lat, W, 1.0 / (om + h), mu_b))
+          - pair(Lam_next, magnetic.step_with_field(lat, W, 1.0 / (om - h), mu_b))) / (2 * h)
+    assert abs(dom - fd) <= 1e-7 * max(1.0, abs(fd))
+    # with no field the adjoint is the plain one
+    from oracle import adjoint
+    L0, d0 = magnetic.step_vjp_with_field(lat, W, Lam_next, tau, np.zeros((3,) + shape))
+    L1, d1 = adjoint.step_vjp(lat, W, Lam_next, tau)
+    assert np.max(np.abs(L0 - L1)) < 1e-15 * np.max(np.abs(L1)) + 1e-300 and abs(d0 - d1) < 1e-13 * abs(d1)
