@@ -327,8 +327,10 @@ int mlbm_spin_loss(mlbm_handle h, const void* W, const double* r_target,
  *              + [k = 0] omega (G_u.(e_j - u) + G_eps(|e_j - u|^2/2 - eps)) / tr rho,
  *   G_u = sum_i G_i dP_i/du,  G_eps = sum_i G_i dP_i/deps,
  *   dL/domega += sum_{x,i,k} g_ik (W_eq_ik - a_ik).
- * Storage MLBM_STORE_F64 or MLBM_STORE_F32 (float fields, double sums);
- * MLBM_STORE_F16DEV and MLBM_EQ_EIGEN are rejected (MLBM_EINVAL).
+ * With a magnetic field the Bloch part of g is first turned back by the
+ * transpose of the cell's rotation.  Storage MLBM_STORE_F64 or MLBM_STORE_F32
+ * (float fields, double sums); MLBM_STORE_F16DEV, an equilibrium mode other
+ * than MLBM_EQ_DIRECT and the positivity limit are rejected (MLBM_EINVAL).
  */
 int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next,
                       void* lam_n, double* dL_domega, void* stream);
