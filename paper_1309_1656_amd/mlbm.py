@@ -321,6 +321,7 @@ def mlbm_set_magnetic_field(h, mu_b):
     """Uniform mu B (three numbers), or None to switch the field off."""
     arr = None if mu_b is None else (ctypes.c_double * 3)(*[float(v) for v in mu_b])
     _check(load_library().mlbm_set_magnetic_field(h.ptr, arr))
+    mlbm_get_info(h)
 
 
 def mlbm_set_magnetic_field_map(h, mu_b):
@@ -328,14 +329,17 @@ def mlbm_set_magnetic_field_map(h, mu_b):
     if mu_b is None:
         _check(load_library().mlbm_set_magnetic_field_map(h.ptr, None))
         h._field_map = None
+        mlbm_get_info(h)
         return
     ptr = _f64_ptr(h, mu_b, 3, "mu_b")
     _check(load_library().mlbm_set_magnetic_field_map(h.ptr, ptr))
     h._field_map = mu_b          # keep the device memory alive while the handle uses it
+    mlbm_get_info(h)
 
 
 def mlbm_set_positivity(h, on):
     _check(load_library().mlbm_set_positivity(h.ptr, int(on)))
+    mlbm_get_info(h)
 
 
 def mlbm_set_launch(h, block_x=0, order=MLBM_ORDER_AUTO, blocks_per_cu=-1):

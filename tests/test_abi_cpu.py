@@ -120,7 +120,14 @@ def test_set_launch_validation_and_info():
     assert h.info["launch_blocks_per_cu"] == 3
     mlbm.mlbm_set_launch(h, 0, mlbm.MLBM_ORDER_AUTO)
     assert h.info["launch_block_x"] in (64, 128)
-    assert h.info["launch_blocks_per_cu"] >= 0
+    assert h.info["launch_blocks_per_cu"] == 2          # FP64 D3Q19 above 64^3
+    # the field and variant kernels run uncapped; the variants with 64-cell blocks
+    mlbm.mlbm_set_magnetic_field(h, [0.1, 0.0, 0.0])
+    assert h.info["launch_blocks_per_cu"] == 0
+    mlbm.mlbm_set_magnetic_field(h, None)
+    mlbm.mlbm_set_launch(h, 128, mlbm.MLBM_ORDER_AUTO, 3)
+    mlbm.mlbm_set_positivity(h, 1)
+    assert h.info["launch_block_x"] == 64 and h.info["launch_blocks_per_cu"] == 0
 
 
 def test_magnetic_field_validation():
