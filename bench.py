@@ -207,11 +207,17 @@ def copy_bandwidth():
 
 
 def kernel_source_hash():
+    """sha256 of the step kernel's code (comments and blank lines removed, so
+    that a comment edit does not invalidate the stored counter readings)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip()).encode())
     return h.hexdigest()
 
 

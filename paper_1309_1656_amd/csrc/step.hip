@@ -17,7 +17,14 @@
 // (2 * 4 * Q * sizeof(T) bytes per cell).  Each wave streams only the Q
 // segments of its channel; the row index and the channel are uniform across
 // a wave, so per-lane addresses are a scalar base plus x.  Stores are
-// non-temporal (the field is not re-read within the pass).
+// non-temporal (the field is not re-read within the pass).  The plain
+// kernels run with a capped number of resident workgroups per CU (see
+// step_launch and lds_for_cap).
+//
+// Template options of k_step: FIELD adds the exact magnetic precession of
+// the Bloch channels after the collision (Sec. 5); VAR selects the isothermal
+// equilibrium (Sec. 3.1) and/or the positivity-limited rate (Sec. 3.3).  Both
+// exchange more data between the waves through LDS and add barriers.
 #include <map>
 #include <mutex>
 #include <utility>
