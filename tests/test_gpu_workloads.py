@@ -174,3 +174,28 @@ def test_convergence_full_size():
     # almost two in eps_tot from its peak (measured 7.7e-4, 4.5e-5, 1.3e-2)
     h0, h1 = hist[0], hist[-1]
     assert h1[0] < 2e-3 * h0[0] and h1[1] < 1e-3 * h0[1] and h1[2] < 5e-2 * hist[:, 2].max()
+
+
+def test_riemann_driver_against_exact_euler():
+    """workloads.riemann (the GPU driver) against the exact Euler solution with
+    the loose bounds that the oracle's run meets (Sec. 4: qualitative only)."""
+    from oracle import euler
+    from paper_1309_1656_amd import workloads
+    wl = synthetic.WORKLOADS["d2q9_riemann"]
+    _flush("riemann driver vs exact Euler")
+    res0 = workloads.riemann(steps=0)
+    res = workloads.riemann()
+    torch.cuda.synchronize()
+    lat = qlbm.Lattice(2)
+    T0, e0 = res0["trrho"], res0["eps"]
+    nx = wl["shape"][1]
+    left = (T0[0, 0], 0.0, T0[0, 0] * e0[0, 0])
+    right = (T0[0, -1], 0.0, T0[0, -1] * e0[0, -1])
+    j = np.arange(nx)
+    t = wl["steps"]
+    r_ex, u_ex, p_ex = euler.sample(2.0, left, right, lat.xi * (j - (nx // 2 - 0.5)) / t)
+    core = (j >= nx // 4) & (j < 3 * nx // 4)
+    rho, p = res["trrho"][0], res["trrho"][0] * res["eps"][0]
+    l1 = lambda a, b: np.abs(a - b)[core].sum() / np.abs(b[core]).sum()
+    assert l1(rho, r_ex) < 0.04 and l1(p, p_ex) < 0.04
+    assert np.max(np.abs(res["trrho"][0] - res["trrho"][1])) < 1e-13     # quasi-1D
