@@ -16,6 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlbm.so")
+C_DEMO_SRC = os.path.join(ROOT, "tests", "c_abi_demo.c")
+C_DEMO = os.path.join(HERE, "mlbm_c_demo")
 SOURCES = ["api.hip", "step.hip", "moments.hip", "init.hip", "adjoint.hip", "eigen.hip"]
 ARCH = "gfx950"
 
@@ -61,7 +63,22 @@ def build(verbose=False):
     if res.returncode != 0:
         raise RuntimeError(f"linking failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
+    build_c_demo()
     return LIB
+
+
+def build_c_demo():
+    """The plain C client of the ABI used by the tests (gcc, linked to libmlbm.so and the HIP runtime)."""
+    if not os.path.exists(C_DEMO_SRC):
+        return None
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(rocm, "include"), C_DEMO_SRC, "-L", HERE, "-lmlbm", "-L", os.path.join(rocm, "lib"),
+           "-lamdhip64", "-lm", "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", C_DEMO]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"building the C client failed:\n{' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    return C_DEMO
 
 
 if __name__ == "__main__":

@@ -17,7 +17,8 @@ def pytest_collection_modifyitems(config, items):
     have_gpu = False
     try:
         import torch
-        have_gpu = torch.cuda.is_available()
+        # counting devices does not initialise the GPU runtime in this process
+        have_gpu = torch.cuda.device_count() > 0
     except Exception:
         have_gpu = False
     if have_gpu:
