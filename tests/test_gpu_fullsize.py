@@ -160,6 +160,39 @@ def test_d3q19_384(storage):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("storage", [mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32])
+def test_d3q19_512_large(storage):
+    """D3Q19 512^3 (134M cells; FP64: two 81.6 GB fields), 3 steps: the largest grid
+    here, past 2^32 field elements.  Conservation, and a sampled oracle step in FP32
+    (FP64 keeps no third field for it)."""
+    shape = (512, 512, 512)
+    f = synthetic.macroscopic_fields(shape, B + 6, device="cuda")
+    sampled = storage == mlbm.MLBM_STORE_F32
+    h = make_handle(shape, tau=0.8, storage=storage)
+    W = h.empty_field()
+    mlbm.mlbm_init_equilibrium(h, W, *_inputs(h, f))
+    del f
+    torch.cuda.empty_cache()
+    g0, _ = mlbm.mlbm_moments(h, W)
+    scratch = h.empty_field()
+    mlbm.mlbm_step(h, W, scratch, 2)
+    Wb = W.clone() if sampled else None
+    mlbm.mlbm_step(h, W, scratch, 1)
+    g1, nneg = mlbm.mlbm_moments(h, W)
+    drift = float(np.abs(g1 - g0).max() / np.abs(g0).max())
+    out = {"drift": drift, "n_neg": nneg}
+    if sampled:
+        out["step"] = sampled_step_error(h, Wb, W, 0.8)
+    _log(f"(512, 512, 512) storage={storage}: {out}")
+    assert nneg == 0
+    if storage == mlbm.MLBM_STORE_F64:
+        assert drift < 1e-13
+    else:
+        assert drift < 1e-9 and out["step"] < 1e-6
+    del W, scratch, Wb, h
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("tau", [0.6, 1.0])
 @pytest.mark.parametrize("storage", [mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32])
 def test_d2q9_1024_shear(tau, storage):
