@@ -164,6 +164,39 @@ def measure_adjoint(warmup):
             "grad_tau": float(tau_t.grad), "grad_W0_norm": float(W0.grad.norm())}
 
 
+GOLDEN_128 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
+                          "oracle_d3q19_128_tau0.8_500.npz")
+
+
+def measure_accuracy(f, storage):
+    """Error of the benchmark workload (D3Q19 128^3, tau 0.8, 500 steps from the
+    same initial state) against the stored FP64 oracle run: normwise over the
+    1 024 stored cells, max over Pauli components of max|d a_k| / max|a_k|.
+    F16 deviation storage is compared on the cell density matrices."""
+    import torch
+    from paper_1309_1656_amd import mlbm
+    if not os.path.exists(GOLDEN_128):
+        return None
+    g = np.load(GOLDEN_128)
+    shape = (128, 128, 128)
+    h = mlbm.mlbm_create(19, dims_of(shape), float(g["meta"][0]), float(g["meta"][2]), storage)
+    W = h.empty_field()
+    mlbm.mlbm_init_equilibrium(h, W, *device_inputs(h, f))
+    mlbm.mlbm_step(h, W, h.empty_field(), int(g["meta"][1]))
+    idx = tuple(torch.from_numpy(c).cuda() for c in np.unravel_index(g["cells"], shape))
+    if storage == mlbm.MLBM_STORE_F16DEV:
+        rho4 = torch.empty((4,) + shape, dtype=torch.float64, device="cuda")
+        mlbm.mlbm_moments(h, W, rho4=rho4)
+        got = rho4[(slice(None),) + idx].cpu().numpy()
+        ref = g["values"].sum(axis=1)
+        err = max(float(np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max()) for k in range(4))
+    else:
+        got = h.pauli_view(W)[(slice(None), slice(None)) + idx].to(torch.float64).cpu().numpy()
+        err = max(float(np.abs(got[k] - g["values"][k]).max() / g["maxabs"][k]) for k in range(4))
+    h.destroy()
+    return err
+
+
 def measure_launch_bound():
     """The Riemann workload (D2Q9 2048 x 2, 385 steps): one mlbm_step call
     launched eagerly against the same call captured once in a HIP graph."""
@@ -319,6 +352,15 @@ def main():
         log(f"  ratio {extras['adjoint']['ratio_to_f64_forward']:.2f}")
         extras["copy_GBps"] = copy_bandwidth()
         log(f"copy {extras['copy_GBps']:.0f} GB/s")
+    if args.workload == "d3q19_128" and not args.skip_extras:
+        log("accuracy against the stored FP64 oracle run")
+        acc = {"reference": "FP64 oracle, same initial state, tau 0.8, 500 steps; 1024 stored cells; "
+                            "max over Pauli components k of max|d a_k| / max|a_k| (FP16: of the density matrix)"}
+        for name, st in (("f64", mlbm.MLBM_STORE_F64), ("fp32", mlbm.MLBM_STORE_F32),
+                         ("f16dev", mlbm.MLBM_STORE_F16DEV)):
+            acc[name] = measure_accuracy(f, st)
+        extras["accuracy_vs_oracle"] = acc
+        log(f"  {acc}")
     Q = 9 if len(shape) == 2 else 19
     grid = "x".join(str(s) for s in reversed(shape))
     line = {
