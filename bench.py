@@ -28,7 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, AMD published peak
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_d3q19_128_traffic.json")
+TRAFFIC_FILES = {"f64": os.path.join(ROOT, "profiles", "k_step_d3q19_128_traffic.json"),
+                 "fp32": os.path.join(ROOT, "profiles", "k_step_d3q19_128_fp32_traffic.json"),
+                 "f16dev": os.path.join(ROOT, "profiles", "k_step_d3q19_128_f16dev_traffic.json")}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1309_1656_amd", "csrc", f) for f in ("step.hip", "common.hpp")]
 
 
@@ -42,7 +44,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="d3q19_128")
-    ap.add_argument("--skip-extras", action="store_true", help="only the FP64 headline measurement")
+    ap.add_argument("--skip-extras", action="store_true", help="only the headline measurement")
+    ap.add_argument("--storage", choices=("f64", "fp32", "f16dev"), default="f64",
+                    help="storage type of the headline measurement (f64 is the benchmark; the others serve "
+                         "per-precision profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for hardware byte counters)")
@@ -254,11 +259,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(storage="f64"):
     """HBM bytes per fused-kernel launch from the stored counter summary, if it matches the current kernel."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES[storage]
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         t = json.load(fh)
     if t.get("kernel_source_sha256") != kernel_source_hash():
         return None
@@ -320,12 +326,15 @@ def main():
     shape, tau = wl["shape"], wl["tau"]
     log(f"workload {args.workload} {shape} tau={tau}: generating inputs")
     f = synthetic.macroscopic_fields(shape, wl["seed"])
-    log("FP64 step")
-    r64 = measure_step(shape, wl["seed"], tau, mlbm.MLBM_STORE_F64, args.steps, args.warmup, f)
+    storage = {"f64": mlbm.MLBM_STORE_F64, "fp32": mlbm.MLBM_STORE_F32, "f16dev": mlbm.MLBM_STORE_F16DEV}[args.storage]
+    log(f"{args.storage} step")
+    r64 = measure_step(shape, wl["seed"], tau, storage, args.steps, args.warmup, f)
     log(f"  {r64['mlups']:.0f} MLUPS, fused {r64['fused_kernel_ms']:.4f} ms, {r64['fused_kernel_GBps']:.0f} GB/s")
     extras = {}
     if not args.skip_extras:
         for name, st in (("fp32", mlbm.MLBM_STORE_F32), ("f16dev", mlbm.MLBM_STORE_F16DEV)):
+            if name == args.storage:
+                continue
             log(f"{name} step")
             extras[name] = measure_step(shape, wl["seed"], tau, st, args.steps, args.warmup, f)
             log(f"  {extras[name]['mlups']:.0f} MLUPS, {extras[name]['fused_kernel_GBps']:.0f} GB/s")
@@ -374,19 +383,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": args.storage,
         "data": "synthetic",
         "config": {"workload": f"{'D2Q9' if Q == 9 else 'D3Q19'} {grid} periodic, tau {tau}, beta0 1, "
-                               f"smooth Fermi-Dirac initial state, FP64 storage",
+                               f"smooth Fermi-Dirac initial state, {args.storage.upper()} storage",
                    "lattice": "D2Q9" if Q == 9 else "D3Q19", "grid": list(reversed(shape)), "tau": tau},
         "roofline": {"bound": "hbm", "achieved": r64["fused_kernel_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r64["fused_kernel_GBps"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.workload == "d3q19_128" else None,
+                     "traffic": measured_traffic(args.storage) if args.workload == "d3q19_128" else None,
                      "algorithmic_bytes_per_launch": r64["bytes_per_cell"] * int(np.prod(shape)),
-                     "kernel": "k_step<19, F64, pull, collide>", "kernel_ms": r64["fused_kernel_ms"],
+                     "kernel": f"k_step<{Q}, {args.storage.upper()}, pull, collide>", "kernel_ms": r64["fused_kernel_ms"],
                      "launch": r64["launch"],
                      "bytes_per_cell": r64["bytes_per_cell"]},
-        "f64": r64,
+        args.storage: r64,
     }
     line.update(extras)
     if not args.no_cpu_baseline:
