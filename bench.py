@@ -13,8 +13,12 @@ roofline fraction, the forward + adjoint time of the differentiable rollout
 (D2Q9 512^2, FP32, 200 steps, checkpoints every 20) next to the plain FP64
 forward, a device-copy bandwidth, and the CPU oracle on a bounded sample.
 
+With --sweep the line also carries "sweep": every step workload (D2Q9 64^2,
+512^2, 1024^2 shear; D3Q19 64^3, 128^3, 384^3) in each storage type it is
+run in, with the automatic launch shape.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-       [--skip-extras] [--no-cpu-baseline]
+       [--storage f64|fp32|f16dev] [--skip-extras] [--no-cpu-baseline] [--sweep]
 """
 import argparse
 import json
@@ -34,6 +38,13 @@ TRAFFIC_FILES = {"f64": os.path.join(ROOT, "profiles", "k_step_d3q19_128_traffic
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1309_1656_amd", "csrc", f) for f in ("step.hip", "common.hpp")]
 
 
+# step workloads (names in paper_1309_1656_amd.synthetic.WORKLOADS) and the storage types the sweep runs them in
+STEP_WORKLOADS = {"d2q9_64": ("f64",), "d2q9_512_adjoint": ("f64", "fp32"), "d2q9_1024_shear": ("f64", "fp32"),
+                  "d3q19_64": ("f64", "fp32", "f16dev"), "d3q19_128": ("f64", "fp32", "f16dev"),
+                  "d3q19_384": ("f64", "fp32", "f16dev")}
+STORAGE_NAMES = ("f64", "fp32", "f16dev")
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -43,12 +54,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="d3q19_128")
+    ap.add_argument("--workload", default="d3q19_128", choices=sorted(STEP_WORKLOADS))
     ap.add_argument("--skip-extras", action="store_true", help="only the headline measurement")
     ap.add_argument("--storage", choices=("f64", "fp32", "f16dev"), default="f64",
                     help="storage type of the headline measurement (f64 is the benchmark; the others serve "
                          "per-precision profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also measure every step workload in each storage type it is run in")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -131,6 +144,38 @@ def measure_step(shape, seed, tau, storage, steps, warmup, f, field=None, isothe
     }
     h.destroy()
     return out
+
+
+def workload_fields(name):
+    """Seeded macroscopic input fields of a step workload."""
+    from paper_1309_1656_amd import synthetic
+    wl = synthetic.WORKLOADS[name]
+    if name == "d2q9_1024_shear":
+        return synthetic.shear_band_fields(wl["shape"], wl["seed"])
+    return synthetic.macroscopic_fields(wl["shape"], wl["seed"])
+
+
+def sweep(warmup):
+    """Every step workload in each storage type it is run in (steps: the
+    workload's own, at most 200 above 5e7 cells)."""
+    import torch
+    from paper_1309_1656_amd import synthetic
+    rows = []
+    for name, storages in STEP_WORKLOADS.items():
+        wl = synthetic.WORKLOADS[name]
+        shape = wl["shape"]
+        f = workload_fields(name)
+        steps = min(wl["steps"], 200) if np.prod(shape) > 5e7 else wl["steps"]
+        for st in storages:
+            log(f"sweep: {name} {st}, {steps} steps")
+            r = measure_step(shape, wl["seed"], wl["tau"], STORAGE_NAMES.index(st), steps, warmup, f)
+            log(f"  {r['mlups']:.0f} MLUPS, fused {r['fused_kernel_GBps']:.0f} GB/s")
+            rows.append({"workload": name, "grid": list(reversed(shape)), "tau": wl["tau"], "storage": st,
+                         "steps": steps, "mlups": r["mlups"], "fused_kernel_ms": r["fused_kernel_ms"],
+                         "fused_kernel_GBps": r["fused_kernel_GBps"], "hbm_frac": r["hbm_frac"],
+                         "launch": r["launch"]})
+            torch.cuda.empty_cache()
+    return rows
 
 
 def measure_adjoint(warmup):
@@ -325,7 +370,7 @@ def main():
     wl = synthetic.WORKLOADS[args.workload]
     shape, tau = wl["shape"], wl["tau"]
     log(f"workload {args.workload} {shape} tau={tau}: generating inputs")
-    f = synthetic.macroscopic_fields(shape, wl["seed"])
+    f = workload_fields(args.workload)
     storage = {"f64": mlbm.MLBM_STORE_F64, "fp32": mlbm.MLBM_STORE_F32, "f16dev": mlbm.MLBM_STORE_F16DEV}[args.storage]
     log(f"{args.storage} step")
     r64 = measure_step(shape, wl["seed"], tau, storage, args.steps, args.warmup, f)
@@ -361,6 +406,8 @@ def main():
         log(f"  ratio {extras['adjoint']['ratio_to_f64_forward']:.2f}")
         extras["copy_GBps"] = copy_bandwidth()
         log(f"copy {extras['copy_GBps']:.0f} GB/s")
+    if args.sweep:
+        extras["sweep"] = sweep(args.warmup)
     if args.workload == "d3q19_128" and not args.skip_extras:
         log("accuracy against the stored FP64 oracle run")
         acc = {"reference": "FP64 oracle, same initial state, tau 0.8, 500 steps; 1024 stored cells; "
