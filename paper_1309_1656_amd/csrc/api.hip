@@ -111,7 +111,7 @@ int ensure_scratch(mlbm_ctx* h, size_t need) {
     }
     if (!h->d_result) {
         if (hipMalloc(&h->d_result, 2 * kRedSlots * sizeof(double)) != hipSuccess)
-            return fail(MLBM_ENOMEM, "cannot allocate %zu bytes of device memory", kRedSlots * sizeof(double));
+            return fail(MLBM_ENOMEM, "cannot allocate %zu bytes of device memory", 2 * kRedSlots * sizeof(double));
     }
     if (hipMalloc(&h->d_partials, need * sizeof(double)) != hipSuccess) {
         h->d_partials = nullptr;

@@ -92,7 +92,9 @@ def test_collide_matches_oracle(shape, inplace):
 
 
 @pytest.mark.parametrize("shape,steps,tau", [((64, 64), 100, 0.8), ((37, 70), 61, 0.6),
-                                              ((13, 9, 11), 40, 0.8), ((6, 5, 70), 25, 1.0)])
+                                              ((13, 9, 11), 40, 0.8), ((6, 5, 70), 25, 1.0),
+                                              # one row / one plane: the y (and z) neighbours wrap onto the cell's own row
+                                              ((1, 300), 30, 0.8), ((1, 1, 300), 20, 0.7), ((2, 1, 129), 20, 0.9)])
 def test_multi_step_f64(shape, steps, tau):
     _flush(f"steps f64 {shape} n={steps}")
     f = fields(shape, 1)
@@ -263,3 +265,44 @@ def test_launch_shapes_give_identical_results(shape, storage):
                     ref = W
                 else:
                     assert torch.equal(W, ref), (bx, order, cap)
+
+
+@pytest.mark.parametrize("shape", [(37, 70), (13, 9, 130)])
+@pytest.mark.parametrize("feature", ["field_map", "isothermal", "positivity"])
+def test_launch_shapes_give_identical_results_with_features(shape, feature):
+    """The magnetic-field and variant kernels under every launch shape: the
+    variants always run 64-cell blocks, the field kernels both widths."""
+    _flush(f"launch shapes {shape} {feature}")
+    f = fields(shape, 23)
+    h = make_handle(shape)
+    if feature == "field_map":
+        bmap = torch.from_numpy(np.random.default_rng(8).normal(0, 0.05, size=(3,) + tuple(shape))).cuda()
+        mlbm.mlbm_set_magnetic_field_map(h, bmap)
+    elif feature == "isothermal":
+        mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_ISOTHERMAL)
+    else:
+        mlbm.mlbm_set_positivity(h, 1)
+    W0 = gpu_init(h, f)
+    if feature == "positivity":
+        # nearly pure spin states (|a_k| = 0.97 a_0 per population), so that the limit acts
+        a = to_pauli_np(h, W0)
+        dirs = np.random.default_rng(9).normal(size=(3,) + a.shape[1:])
+        a[1:] = 0.97 * a[0][None] * dirs / np.linalg.norm(dirs, axis=0)
+        W0 = from_pauli(h, a)
+    ref = None
+    for bx in (64, 128):
+        for order in (mlbm.MLBM_ORDER_NATURAL, mlbm.MLBM_ORDER_XCD_RANGE, mlbm.MLBM_ORDER_INTERLEAVE8):
+            for cap in (0, 2):
+                mlbm.mlbm_set_launch(h, bx, order, cap)
+                W = W0.clone()
+                mlbm.mlbm_step(h, W, h.empty_field(), 3)
+                torch.cuda.synchronize()
+                if ref is None:
+                    ref = W
+                else:
+                    assert torch.equal(W, ref), (bx, order, cap)
+    if feature == "positivity":
+        mlbm.mlbm_set_positivity(h, 0)
+        W = W0.clone()
+        mlbm.mlbm_step(h, W, h.empty_field(), 3)
+        assert not torch.equal(W, ref)      # the limit acted
