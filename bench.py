@@ -214,6 +214,27 @@ def measure_adjoint(warmup):
             "grad_tau": float(tau_t.grad), "grad_W0_norm": float(W0.grad.norm())}
 
 
+def measure_adjoint_step(shape, tau, f, storage, reps=10):
+    """One mlbm_adjoint_step (W_n as stored, lam_{n+1} pulled, dL/domega finalised) on a 3-D workload:
+    average ms and the rate of its algorithmic bytes (read W_n and lam_{n+1}, write lam_n: 3 4 Q s per cell)."""
+    import torch
+    from paper_1309_1656_amd import mlbm
+    Q = 19
+    h = mlbm.mlbm_create(Q, dims_of(shape), tau, 1.0, storage)
+    W = h.empty_field()
+    mlbm.mlbm_init_equilibrium(h, W, *device_inputs(h, f))
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    lam1 = torch.randn(h.field_shape, dtype=h.field_dtype, device="cuda", generator=gen)
+    lam0 = h.empty_field()
+    dom = torch.zeros(1, dtype=torch.float64, device="cuda")
+    mlbm.mlbm_adjoint_step(h, W, lam1, lam0, dom)
+    t = time_region(lambda: mlbm.mlbm_adjoint_step(h, W, lam1, lam0, dom), reps=reps)
+    N = int(np.prod(shape))
+    by = 3 * 4 * Q * {0: 8, 1: 4}[storage] * N
+    h.destroy()
+    return {"ms": t, "GBps": by / (t * 1e-3) / 1e9, "hbm_frac": by / (t * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 GOLDEN_128 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden",
                           "oracle_d3q19_128_tau0.8_500.npz")
 
@@ -404,6 +425,14 @@ def main():
         log("forward + adjoint rollout")
         extras["adjoint"] = measure_adjoint(args.warmup)
         log(f"  ratio {extras['adjoint']['ratio_to_f64_forward']:.2f}")
+        if args.workload == "d3q19_128":
+            log("adjoint step, D3Q19 128^3")
+            adj3 = {"workload": "D3Q19 128^3, one mlbm_adjoint_step", "f64_fused_forward_ms": r64["fused_kernel_ms"]}
+            for name, st in (("f64", mlbm.MLBM_STORE_F64), ("fp32", mlbm.MLBM_STORE_F32)):
+                adj3[name] = measure_adjoint_step(shape, tau, f, st)
+                adj3[name]["ratio_to_f64_forward_pass"] = adj3[name]["ms"] / r64["fused_kernel_ms"]
+                log(f"  {name}: {adj3[name]['ms'] * 1e3:.1f} us, {adj3[name]['GBps']:.0f} GB/s")
+            extras["adjoint"]["d3q19_128_step"] = adj3
         extras["copy_GBps"] = copy_bandwidth()
         log(f"copy {extras['copy_GBps']:.0f} GB/s")
     if args.sweep:
