@@ -347,23 +347,37 @@ def copy_probe():
     torch.cuda.synchronize()
 
 
+def _oracle_rate(lat, f, tau, min_steps, seconds):
+    from oracle import qlbm
+    W = qlbm.init_equilibrium(lat, f["trrho"], f["r"], lat.xi * f["u_lat"], f["T"])
+    W = qlbm.step(lat, W, tau)           # warm-up
+    n, t0 = 0, time.perf_counter()
+    while n < min_steps or time.perf_counter() - t0 < seconds:
+        W = qlbm.step(lat, W, tau)
+        n += 1
+    dt = time.perf_counter() - t0
+    return int(np.prod(f["T"].shape)) * n / dt / 1e6, n
+
+
 def cpu_baseline(seconds=12.0):
-    """The FP64 oracle on a bounded sample: D3Q19 48^3 cells, steps until ~seconds."""
+    """The FP64 oracle on a bounded sample: D3Q19 48^3 cells, steps until ~seconds;
+    also its rate on the smaller step workloads (a few steps each)."""
+    from threadpoolctl import threadpool_limits
     from oracle import qlbm
     from paper_1309_1656_amd import synthetic
     shape = (48, 48, 48)
-    lat = qlbm.Lattice(3)
-    f = synthetic.macroscopic_fields(shape, synthetic.BASE_SEED + 3)
-    W = qlbm.init_equilibrium(lat, f["trrho"], f["r"], lat.xi * f["u_lat"], f["T"])
-    W = qlbm.step(lat, W, 0.8)           # warm-up
-    n, t0 = 0, time.perf_counter()
-    while n < 3 or time.perf_counter() - t0 < seconds:
-        W = qlbm.step(lat, W, 0.8)
-        n += 1
-    dt = time.perf_counter() - t0
-    return {"value": int(np.prod(shape)) * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+    with threadpool_limits(limits=1):    # the oracle is elementwise NumPy; hold any library pool to one thread
+        rate, n = _oracle_rate(qlbm.Lattice(3), synthetic.macroscopic_fields(shape, synthetic.BASE_SEED + 3), 0.8,
+                               3, seconds)
+        per = {}
+        for name, lat_d, steps in (("d2q9_64", 2, 20), ("d2q9_1024_shear", 2, 2), ("d3q19_64", 3, 3)):
+            wl = synthetic.WORKLOADS[name]
+            per[name] = {"MLUPS": _oracle_rate(qlbm.Lattice(lat_d), workload_fields(name), wl["tau"], steps, 0.0)[0],
+                         "steps": steps}
+    return {"value": rate, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"D3Q19 48^3 cells, {n} steps, tau 0.8, same initial-state family as the workload; "
                       "NumPy elementwise work, one thread",
+            "per_workload": per,
             "host_cpus": os.cpu_count(), "host_cpu_model": _cpu_model()}
 
 
