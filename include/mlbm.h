@@ -402,6 +402,16 @@ int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps,
  */
 int mlbm_set_f16_reference(mlbm_handle h, const double* ref, double scale);
 
+/*
+ * mlbm_device_copy -- diagnostic, not part of the method: a plain copy of
+ * `bytes` bytes from src to dst (device memory, 16-byte aligned, not
+ * overlapping; bytes a multiple of 16, at most 2^35), one 16-byte vector per
+ * thread with streaming loads and stores, enqueued on `stream`.  Its rate is
+ * the achievable-bandwidth reference next to the step's fraction of the HBM
+ * peak.  MLBM_EINVAL on a violated requirement (nothing enqueued).
+ */
+int mlbm_device_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 /* mlbm_last_error -- message of the last failed call on this thread ("" if none). */
 const char* mlbm_last_error(void);
 

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlbm.so")
 C_DEMO_SRC = os.path.join(ROOT, "tests", "c_abi_demo.c")
 C_DEMO = os.path.join(HERE, "mlbm_c_demo")
-SOURCES = ["api.hip", "step.hip", "moments.hip", "init.hip", "adjoint.hip", "eigen.hip"]
+SOURCES = ["api.hip", "step.hip", "moments.hip", "init.hip", "adjoint.hip", "eigen.hip", "copy.hip"]
 ARCH = "gfx950"
 
 

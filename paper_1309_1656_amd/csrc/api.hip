@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -586,6 +587,18 @@ int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps,
     }
     if (dL_domega) HIP_TRY(launch_finalize(h->d_partials, nb, 1, 0u, nullptr, dL_domega, 1.0, s));
     if (in != lam) HIP_TRY(hipMemcpyAsync(lam, in, fb, hipMemcpyDeviceToDevice, s));
+    return ok();
+}
+
+int mlbm_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst) return fail(MLBM_EINVAL, "null pointer");
+    if (bytes % 16 != 0) return fail(MLBM_EINVAL, "bytes must be a multiple of 16 (got %zu)", bytes);
+    const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+    if (a % 16 != 0 || b % 16 != 0) return fail(MLBM_EINVAL, "src and dst must be 16-byte aligned");
+    if (a < b + bytes && b < a + bytes && bytes > 0) return fail(MLBM_EINVAL, "src and dst overlap");
+    // one thread per 16 bytes and at most 2^31 threads in the grid
+    if (bytes > (static_cast<size_t>(1) << 35)) return fail(MLBM_EINVAL, "at most 2^35 bytes per call");
+    HIP_TRY(launch_copy16(src, dst, bytes / 16, as_stream(stream)));
     return ok();
 }
 

@@ -73,4 +73,7 @@ hipError_t launch_finalize(const double* partials, int nblocks, int stride, unsi
 // Number of blocks (= partials) of launch_adjoint for a grid.
 int adjoint_blocks(int nx, int ny, int nz);
 
+// Flat copy of n16 16-byte vectors (16-byte aligned, non-overlapping).
+hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s);
+
 }  // namespace mlbm

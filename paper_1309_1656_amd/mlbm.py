@@ -24,7 +24,7 @@ EXPORTS = (
     "mlbm_init_equilibrium", "mlbm_step", "mlbm_collide", "mlbm_stream", "mlbm_moments", "mlbm_spin_loss",
     "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_set_f16_reference", "mlbm_set_launch",
     "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_init_chemical", "mlbm_relaxation", "mlbm_set_positivity",
-    "mlbm_last_error",
+    "mlbm_device_copy", "mlbm_last_error",
 )
 
 
@@ -83,6 +83,7 @@ def load_library(path=LIB_PATH):
         "mlbm_init_chemical": ([vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_relaxation": ([vp, vp, dp, vp], ctypes.c_int),
         "mlbm_set_positivity": ([vp, ctypes.c_int], ctypes.c_int),
+        "mlbm_device_copy": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "mlbm_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -358,6 +359,15 @@ def mlbm_adjoint_segment(h, W, states, nsteps, lam, lam_tmp, dL_domega=None, str
         h.ptr, _field_ptr(h, W, "W"), None if states is None else _dev_ptr(states, name="states"), int(nsteps),
         _field_ptr(h, lam, "lam"), _field_ptr(h, lam_tmp, "lam_tmp"),
         _dev_ptr(dL_domega, torch.float64, 1, "dL_domega"), _stream_ptr(stream)))
+
+
+def mlbm_device_copy(src, dst, nbytes=None, stream=None):
+    """Diagnostic plain copy of nbytes (default: all of src) between two device tensors."""
+    n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    if n > src.numel() * src.element_size() or n > dst.numel() * dst.element_size():
+        raise MlbmError(MLBM_EINVAL, "nbytes exceeds a tensor")
+    _check(load_library().mlbm_device_copy(_dev_ptr(src, name="src"), _dev_ptr(dst, name="dst"), n,
+                                           _stream_ptr(stream)))
 
 
 def mlbm_set_f16_reference(h, ref, scale):

@@ -180,3 +180,14 @@ def test_variant_validation():
         mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_ISOTHERMAL)
     with pytest.raises(mlbm.MlbmError):
         mlbm.mlbm_set_eq_mode(h, 3)
+
+
+def test_device_copy_validation():
+    """Requirements of the diagnostic copy are checked on the host before anything is enqueued."""
+    lib = mlbm.load_library()
+    cases = [(0, 4096, 64, "null"), (4096, 0, 64, "null"), (4096, 8192, 24, "multiple of 16"),
+             (4104, 8192, 64, "aligned"), (4096, 4160, 128, "overlap"), (4096, 1 << 40, (1 << 35) + 16, "2^35")]
+    for src, dst, n, msg in cases:
+        rc = lib.mlbm_device_copy(ctypes.c_void_p(src), ctypes.c_void_p(dst), n, None)
+        assert rc == mlbm.MLBM_EINVAL, (src, dst, n)
+        assert msg in mlbm.mlbm_last_error(), mlbm.mlbm_last_error()

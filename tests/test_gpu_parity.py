@@ -306,3 +306,16 @@ def test_launch_shapes_give_identical_results_with_features(shape, feature):
         W = W0.clone()
         mlbm.mlbm_step(h, W, h.empty_field(), 3)
         assert not torch.equal(W, ref)      # the limit acted
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 16, (1 << 20) + 48])
+def test_device_copy_is_exact(nbytes):
+    """The diagnostic copy moves exactly nbytes and touches nothing after them."""
+    _flush(f"device copy {nbytes} bytes")
+    gen = torch.Generator(device="cuda").manual_seed(nbytes)
+    src = torch.randint(0, 256, (nbytes + 64,), dtype=torch.uint8, device="cuda", generator=gen)
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+    mlbm.mlbm_device_copy(src, dst, nbytes)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src[:nbytes])
+    assert int(dst[nbytes:].count_nonzero()) == 0
