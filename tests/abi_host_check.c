@@ -89,6 +89,11 @@ int main(void) {
     EXPECT(mlbm_init_chemical(h, p1, NULL, NULL, p2, p2, NULL), MLBM_EINVAL);
     EXPECT(mlbm_relaxation(h, p1, NULL, NULL), MLBM_EINVAL);
     EXPECT(mlbm_spin_loss(h16, p1, p2, NULL, NULL, NULL), MLBM_EINVAL);
+    EXPECT(mlbm_device_copy(NULL, p2, 64, NULL), MLBM_EINVAL);
+    EXPECT(mlbm_device_copy(p1, p2, 24, NULL), MLBM_EINVAL);                /* not a multiple of 16 */
+    EXPECT(mlbm_device_copy((void*)0x1008, p2, 64, NULL), MLBM_EINVAL);     /* misaligned */
+    EXPECT(mlbm_device_copy(p1, (void*)0x1040, 128, NULL), MLBM_EINVAL);    /* overlapping */
+    EXPECT(mlbm_device_copy(p1, p2, 0, NULL), MLBM_OK);                     /* nothing to copy */
 
     mlbm_destroy(h);
     mlbm_destroy(h2);
