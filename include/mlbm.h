@@ -249,6 +249,23 @@ int mlbm_init_chemical(mlbm_handle h, void* W, const double* nu, const double* a
 int mlbm_step(mlbm_handle h, void* W, void* scratch, int nsteps, void* stream);
 
 /*
+ * mlbm_step_states -- the same nsteps time steps (Sec. 3.3) out of place,
+ * keeping the intermediate states.  src holds the pre-collision state W(t)
+ * and is only read; dst receives W(t + nsteps).  `states` is caller-owned
+ * device memory for nstates fields laid out one after the other: the
+ * post-collision state of step j (j = 0 .. nsteps - 1) is written to field
+ * j mod nstates, so nstates >= nsteps keeps all of them (the layout
+ * mlbm_adjoint_sweep reads) and nstates = 2 is a plain ping-pong.  Passes:
+ * one collide-only, nsteps - 1 fused, one stream-only, as in mlbm_step; no
+ * copy, except that nsteps = 0 copies src to dst.  Only kernel launches (or
+ * that one copy) are enqueued.
+ * Errors: MLBM_EINVAL (null pointers, nsteps < 0, nstates < 1, or < 2 with
+ * more than one step, src = dst, src or dst inside the states), MLBM_EHIP.
+ */
+int mlbm_step_states(mlbm_handle h, const void* src, void* dst, void* states, int nstates, int nsteps,
+                     void* stream);
+
+/*
  * mlbm_collide -- dst = C(src), the BGK collision of Eq. CollisionStep cell
  * by cell (as configured on the handle), no streaming.  dst may equal src
  * (in place).
@@ -394,6 +411,18 @@ int mlbm_set_launch(mlbm_handle h, int block_x, int order, int blocks_per_cu);
  */
 int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps, void* lam,
                          void* lam_tmp, double* dL_domega, void* stream);
+
+/*
+ * mlbm_adjoint_sweep -- the reverse half of mlbm_adjoint_segment: the same
+ * nsteps adjoint steps, from the last to the first, with the intermediate
+ * states already in `states` (fields 0 .. nsteps - 2: the post-collision
+ * states of steps 0 .. nsteps - 2 after W, as mlbm_step_states writes them
+ * with nstates >= nsteps - 1; read only).  For the segment whose states the
+ * forward pass kept, so that it needs no recomputation.  Arguments, result
+ * and restrictions otherwise as mlbm_adjoint_segment.
+ */
+int mlbm_adjoint_sweep(mlbm_handle h, const void* W, const void* states, int nsteps, void* lam,
+                       void* lam_tmp, double* dL_domega, void* stream);
 
 /*
  * mlbm_set_f16_reference -- restore the MLBM_STORE_F16DEV reference R (4*Q

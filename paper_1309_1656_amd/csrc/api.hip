@@ -457,6 +457,41 @@ int mlbm_step(mlbm_handle h, void* W, void* scratch, int nsteps, void* stream) {
     return ok();
 }
 
+int mlbm_step_states(mlbm_handle h, const void* src, void* dst, void* states, int nstates, int nsteps,
+                     void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!src || !dst) return fail(MLBM_EINVAL, "null field");
+    if (nsteps < 0) return fail(MLBM_EINVAL, "nsteps must be >= 0");
+    if (src == dst) return fail(MLBM_EINVAL, "src and dst must be distinct");
+    size_t fb = 0;
+    mlbm_field_bytes(h, &fb);
+    hipStream_t s = as_stream(stream);
+    if (nsteps == 0) {
+        HIP_TRY(hipMemcpyAsync(dst, src, fb, hipMemcpyDeviceToDevice, s));
+        return ok();
+    }
+    if (!states) return fail(MLBM_EINVAL, "null states");
+    if (nstates < 1 || (nsteps > 1 && nstates < 2))
+        return fail(MLBM_EINVAL, "need nstates >= 1, and >= 2 for more than one step (got %d)", nstates);
+    const uintptr_t a = reinterpret_cast<uintptr_t>(states), end = a + static_cast<uintptr_t>(nstates) * fb;
+    auto inside = [&](const void* q) {
+        const uintptr_t u = reinterpret_cast<uintptr_t>(q);
+        return u + fb > a && u < end;
+    };
+    if (inside(src) || inside(dst)) return fail(MLBM_EINVAL, "src and dst must not overlap the states");
+    const bool eig = h->eq_mode == MLBM_EQ_EIGEN;
+    auto run = [&](StepKind kind, const void* x, void* y) -> hipError_t {
+        if (eig && kind != StepKind::StreamOnly) return launch_step_eigen(kind, h->Q, x, y, h->kp, h->fp, nullptr, s);
+        return launch_step(kind, h->Q, h->storage, x, y, h->kp, h->fp, h->launch, s);
+    };
+    char* st = static_cast<char*>(states);
+    auto slot = [&](int j) { return st + static_cast<size_t>(j % nstates) * fb; };
+    HIP_TRY(run(StepKind::CollideOnly, src, slot(0)));
+    for (int j = 1; j < nsteps; ++j) HIP_TRY(run(StepKind::Fused, slot(j - 1), slot(j)));
+    HIP_TRY(run(StepKind::StreamOnly, slot(nsteps - 1), dst));
+    return ok();
+}
+
 int mlbm_collide(mlbm_handle h, const void* src, void* dst, void* stream) {
     if (int e = check_handle(h)) return e;
     if (!src || !dst) return fail(MLBM_EINVAL, "null field");
@@ -552,8 +587,8 @@ int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next, void
     return ok();
 }
 
-int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps, void* lam, void* lam_tmp,
-                         double* dL_domega, void* stream) {
+// Checks shared by mlbm_adjoint_segment and mlbm_adjoint_sweep; also sizes the partials.
+static int adjoint_checks(mlbm_handle h, const void* W, const void* states, int nsteps, void* lam, void* lam_tmp) {
     if (int e = check_handle(h)) return e;
     if (!W || !lam || !lam_tmp || (nsteps > 1 && !states)) return fail(MLBM_EINVAL, "null field");
     if (nsteps < 0) return fail(MLBM_EINVAL, "nsteps must be >= 0");
@@ -561,25 +596,24 @@ int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps,
     if (h->eq_mode != MLBM_EQ_DIRECT || h->positivity)
         return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode without the positivity limit");
     if (lam == lam_tmp || lam == W || lam_tmp == W) return fail(MLBM_EINVAL, "lam, lam_tmp and W must be distinct");
-    if (nsteps == 0) return ok();
+    if (nsteps == 0) return MLBM_OK;
     const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));
-    if (int e = ensure_scratch(h, std::max<size_t>(static_cast<size_t>(nb), static_cast<size_t>(kRedBlocks) * kRedSlots)))
-        return e;
-    hipStream_t s = as_stream(stream);
+    return ensure_scratch(h, std::max<size_t>(static_cast<size_t>(nb), static_cast<size_t>(kRedBlocks) * kRedSlots));
+}
+
+// Reverse sweep over nsteps adjoint steps: step j reads W_j, gathered from
+// states[j - 1] (post-collision) for j >= 1 and W itself for j = 0.
+static int adjoint_reverse(mlbm_handle h, const void* W, const char* st, int nsteps, void* lam, void* lam_tmp,
+                           double* dL_domega, hipStream_t s) {
+    const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));
     size_t fb = 0;
     mlbm_field_bytes(h, &fb);
-    char* st = static_cast<char*>(states);
-    // forward recomputation: states[j] = post-collision state of step j (j = 0 .. nsteps - 2)
-    if (nsteps > 1) HIP_TRY(launch_step(StepKind::CollideOnly, h->Q, h->storage, W, st, h->kp, h->fp, h->launch, s));
-    for (int j = 1; j < nsteps - 1; ++j)
-        HIP_TRY(launch_step(StepKind::Fused, h->Q, h->storage, st + (j - 1) * fb, st + j * fb, h->kp, h->fp, h->launch, s));
-    // reverse sweep: step j reads W_j, gathered from states[j - 1] for j >= 1
     void* in = lam;
     void* out = lam_tmp;
     for (int j = nsteps - 1; j >= 0; --j) {
         const bool pulled = j > 0;
         const void* wsrc = pulled ? static_cast<const void*>(st + (j - 1) * fb) : W;
-        // block partials of dL/domega accumulate over the segment: one final sum
+        // block partials of dL/domega accumulate over the sweep: one final sum
         HIP_TRY(launch_adjoint(h->Q, h->storage, pulled, wsrc, in, out, h->kp, h->d_partials, j < nsteps - 1, s));
         void* t = in;
         in = out;
@@ -588,6 +622,29 @@ int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps,
     if (dL_domega) HIP_TRY(launch_finalize(h->d_partials, nb, 1, 0u, nullptr, dL_domega, 1.0, s));
     if (in != lam) HIP_TRY(hipMemcpyAsync(lam, in, fb, hipMemcpyDeviceToDevice, s));
     return ok();
+}
+
+int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps, void* lam, void* lam_tmp,
+                         double* dL_domega, void* stream) {
+    if (int e = adjoint_checks(h, W, states, nsteps, lam, lam_tmp)) return e;
+    if (nsteps == 0) return ok();
+    hipStream_t s = as_stream(stream);
+    size_t fb = 0;
+    mlbm_field_bytes(h, &fb);
+    char* st = static_cast<char*>(states);
+    // forward recomputation: states[j] = post-collision state of step j (j = 0 .. nsteps - 2)
+    if (nsteps > 1) HIP_TRY(launch_step(StepKind::CollideOnly, h->Q, h->storage, W, st, h->kp, h->fp, h->launch, s));
+    for (int j = 1; j < nsteps - 1; ++j)
+        HIP_TRY(launch_step(StepKind::Fused, h->Q, h->storage, st + (j - 1) * fb, st + j * fb, h->kp, h->fp, h->launch, s));
+    return adjoint_reverse(h, W, st, nsteps, lam, lam_tmp, dL_domega, s);
+}
+
+int mlbm_adjoint_sweep(mlbm_handle h, const void* W, const void* states, int nsteps, void* lam, void* lam_tmp,
+                       double* dL_domega, void* stream) {
+    if (int e = adjoint_checks(h, W, states, nsteps, lam, lam_tmp)) return e;
+    if (nsteps == 0) return ok();
+    return adjoint_reverse(h, W, static_cast<const char*>(states), nsteps, lam, lam_tmp, dL_domega,
+                           as_stream(stream));
 }
 
 int mlbm_device_copy(const void* src, void* dst, size_t bytes, void* stream) {

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmlbm.so"
 EXPORTS = (
     "mlbm_create", "mlbm_destroy", "mlbm_get_info", "mlbm_field_bytes", "mlbm_set_tau", "mlbm_set_eq_mode",
     "mlbm_init_equilibrium", "mlbm_step", "mlbm_collide", "mlbm_stream", "mlbm_moments", "mlbm_spin_loss",
-    "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_set_f16_reference", "mlbm_set_launch",
+    "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_step_states", "mlbm_adjoint_sweep", "mlbm_set_f16_reference", "mlbm_set_launch",
     "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_init_chemical", "mlbm_relaxation", "mlbm_set_positivity",
     "mlbm_device_copy", "mlbm_last_error",
 )
@@ -76,6 +76,8 @@ def load_library(path=LIB_PATH):
         "mlbm_spin_loss": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_adjoint_step": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_adjoint_segment": ([vp, vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
+        "mlbm_adjoint_sweep": ([vp, vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
+        "mlbm_step_states": ([vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
         "mlbm_set_f16_reference": ([vp, dp, ctypes.c_double], ctypes.c_int),
         "mlbm_set_launch": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "mlbm_set_magnetic_field": ([vp, dp], ctypes.c_int),
@@ -266,6 +268,27 @@ def mlbm_step(h, W, scratch, nsteps, stream=None):
                                     int(nsteps), _stream_ptr(stream)))
 
 
+def _states_ptr(h, states, nfields, what):
+    """Device pointer of a contiguous tensor holding at least nfields fields (None when nfields <= 0)."""
+    if nfields <= 0 and states is None:
+        return None
+    need = nfields * 4 * h.Q * h.info["ncell"]
+    if states is None or states.dtype != h.field_dtype or states.numel() < need or not states.is_contiguous():
+        raise MlbmError(MLBM_EINVAL, f"{what} must hold {nfields} contiguous fields")
+    return _dev_ptr(states, name=what)
+
+
+def mlbm_step_states(h, src, dst, states, nsteps, nstates=None, stream=None):
+    """Out-of-place steps keeping the post-collision states: step j's goes to field j mod nstates of
+    `states` (default nstates: the number of fields the tensor holds)."""
+    if nstates is None:
+        nstates = 0 if states is None else states.numel() // (4 * h.Q * h.info["ncell"])
+    _check(load_library().mlbm_step_states(
+        h.ptr, _field_ptr(h, src, "src"), _field_ptr(h, dst, "dst"),
+        _states_ptr(h, states, nstates if nsteps > 0 else 0, "states"), int(nstates), int(nsteps),
+        _stream_ptr(stream)))
+
+
 def mlbm_collide(h, src, dst, stream=None):
     _check(load_library().mlbm_collide(h.ptr, _field_ptr(h, src, "src"), _field_ptr(h, dst, "dst"),
                                        _stream_ptr(stream)))
@@ -357,6 +380,15 @@ def mlbm_adjoint_segment(h, W, states, nsteps, lam, lam_tmp, dL_domega=None, str
             raise MlbmError(MLBM_EINVAL, f"states must hold {nsteps - 1} contiguous fields")
     _check(load_library().mlbm_adjoint_segment(
         h.ptr, _field_ptr(h, W, "W"), None if states is None else _dev_ptr(states, name="states"), int(nsteps),
+        _field_ptr(h, lam, "lam"), _field_ptr(h, lam_tmp, "lam_tmp"),
+        _dev_ptr(dL_domega, torch.float64, 1, "dL_domega"), _stream_ptr(stream)))
+
+
+def mlbm_adjoint_sweep(h, W, states, nsteps, lam, lam_tmp, dL_domega=None, stream=None):
+    """states: the nsteps - 1 post-collision states after W (e.g. from mlbm_step_states), or None for nsteps <= 1."""
+    import torch
+    _check(load_library().mlbm_adjoint_sweep(
+        h.ptr, _field_ptr(h, W, "W"), _states_ptr(h, states, nsteps - 1, "states"), int(nsteps),
         _field_ptr(h, lam, "lam"), _field_ptr(h, lam_tmp, "lam_tmp"),
         _dev_ptr(dL_domega, torch.float64, 1, "dL_domega"), _stream_ptr(stream)))
 

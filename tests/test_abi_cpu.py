@@ -191,3 +191,38 @@ def test_device_copy_validation():
         rc = lib.mlbm_device_copy(ctypes.c_void_p(src), ctypes.c_void_p(dst), n, None)
         assert rc == mlbm.MLBM_EINVAL, (src, dst, n)
         assert msg in mlbm.mlbm_last_error(), mlbm.mlbm_last_error()
+
+
+def test_step_states_and_sweep_validation():
+    """Argument checks of mlbm_step_states and mlbm_adjoint_sweep (nothing is enqueued)."""
+    h = mlbm.mlbm_create(9, (8, 8, 1), 0.8, 1.0, mlbm.MLBM_STORE_F32)
+    lib = mlbm.load_library()
+    fb = 4 * 9 * 64 * 4
+    src, dst = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20)
+    st = ctypes.c_void_p(4 << 20)
+    cases = [
+        ((h.ptr, None, dst, st, 2, 3, None), "null field"),
+        ((h.ptr, src, src, st, 2, 3, None), "distinct"),
+        ((h.ptr, src, dst, st, 2, -1, None), "nsteps"),
+        ((h.ptr, src, dst, None, 2, 3, None), "null states"),
+        ((h.ptr, src, dst, st, 1, 3, None), "nstates"),
+        ((h.ptr, src, dst, st, 0, 1, None), "nstates"),
+        ((h.ptr, ctypes.c_void_p((4 << 20) + fb), dst, st, 2, 3, None), "overlap"),
+        ((h.ptr, src, ctypes.c_void_p((4 << 20) + fb // 2), st, 2, 3, None), "overlap"),
+    ]
+    for args, msg in cases:
+        assert lib.mlbm_step_states(*args) == mlbm.MLBM_EINVAL, msg
+        assert msg in mlbm.mlbm_last_error(), (msg, mlbm.mlbm_last_error())
+    # a field just after the states does not overlap them (rejected only for the step count here)
+    assert lib.mlbm_step_states(h.ptr, ctypes.c_void_p((4 << 20) + 2 * fb), dst, st, 2, -1, None) == mlbm.MLBM_EINVAL
+    assert "nsteps" in mlbm.mlbm_last_error()
+    lam, tmp = ctypes.c_void_p(8 << 20), ctypes.c_void_p(9 << 20)
+    assert lib.mlbm_adjoint_sweep(h.ptr, src, None, 3, lam, tmp, None, None) == mlbm.MLBM_EINVAL
+    assert lib.mlbm_adjoint_sweep(h.ptr, src, st, 3, lam, lam, None, None) == mlbm.MLBM_EINVAL
+    assert lib.mlbm_adjoint_sweep(h.ptr, src, st, -2, lam, tmp, None, None) == mlbm.MLBM_EINVAL
+    assert lib.mlbm_adjoint_sweep(h.ptr, src, None, 0, lam, tmp, None, None) == mlbm.MLBM_OK   # nothing to do
+    h16 = mlbm.mlbm_create(9, (8, 8, 1), 0.8, 1.0, mlbm.MLBM_STORE_F16DEV)
+    assert lib.mlbm_adjoint_sweep(h16.ptr, src, st, 3, lam, tmp, None, None) == mlbm.MLBM_EINVAL
+    mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_ISOTHERMAL)
+    assert lib.mlbm_adjoint_sweep(h.ptr, src, st, 3, lam, tmp, None, None) == mlbm.MLBM_EINVAL
+    assert "direct equilibrium" in mlbm.mlbm_last_error()

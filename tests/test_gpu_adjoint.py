@@ -148,3 +148,88 @@ def test_adjoint_segment_equals_stepwise(shape, n):
     # the segment sums dL/domega per block over all steps before the one final
     # sum, the stepwise calls per step: same terms, other rounding order
     assert abs(dom_a.item() - dom_b.item()) <= 1e-13 * abs(dom_a.item())
+
+
+@pytest.mark.parametrize("shape", [(37, 70), (13, 9, 11)])
+@pytest.mark.parametrize("n", [0, 1, 2, 5])
+def test_step_states_equals_step(shape, n):
+    """mlbm_step_states (out of place, nstates = 2 or n) gives mlbm_step's result bit for bit and
+    keeps the post-collision states: streaming state j gives the state after j + 1 steps."""
+    print(f"step_states {shape} n={n}", flush=True)
+    f = fields(shape, 41)
+    h = make_handle(shape, tau=0.7)
+    W0 = gpu_init(h, f)
+    ref = W0.clone()
+    mlbm.mlbm_step(h, ref, h.empty_field(), n)
+    for nstates in sorted({2, max(n, 1)}):
+        states = torch.empty((nstates,) + tuple(W0.shape), dtype=W0.dtype, device="cuda")
+        W0_copy = W0.clone()
+        out = h.empty_field()
+        mlbm.mlbm_step_states(h, W0, out, states, n, nstates=nstates)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        assert torch.equal(W0, W0_copy)          # src is read only
+        if nstates >= n:
+            for j in range(n):
+                after = W0.clone()
+                mlbm.mlbm_step(h, after, h.empty_field(), j + 1)
+                streamed = h.empty_field()
+                mlbm.mlbm_stream(h, states[j], streamed)
+                assert torch.equal(streamed, after), j
+
+
+@pytest.mark.parametrize("shape,n", [((37, 70), 7), ((13, 9, 11), 4), ((16, 16), 1)])
+def test_adjoint_sweep_equals_segment(shape, n):
+    """mlbm_adjoint_sweep on states kept by mlbm_step_states == mlbm_adjoint_segment (which recomputes them)."""
+    f = fields(shape, 43)
+    h = make_handle(shape, tau=0.7)
+    W0 = gpu_init(h, f)
+    rng = np.random.default_rng(7)
+    lamN = from_pauli(h, rng.standard_normal((4, h.Q) + tuple(shape)))
+    states = torch.empty((max(n, 2),) + tuple(W0.shape), dtype=W0.dtype, device="cuda")
+    mlbm.mlbm_step_states(h, W0, h.empty_field(), states, n, nstates=n)
+    lam_a = lamN.clone()
+    dom_a = torch.zeros(1, dtype=torch.float64, device="cuda")
+    mlbm.mlbm_adjoint_sweep(h, W0, states if n > 1 else None, n, lam_a, h.empty_field(), dom_a)
+    lam_b = lamN.clone()
+    dom_b = torch.zeros(1, dtype=torch.float64, device="cuda")
+    buf = torch.empty((max(n - 1, 1),) + tuple(W0.shape), dtype=W0.dtype, device="cuda")
+    mlbm.mlbm_adjoint_segment(h, W0, buf if n > 1 else None, n, lam_b, h.empty_field(), dom_b)
+    assert torch.equal(lam_a, lam_b)
+    assert dom_a.item() == dom_b.item()
+
+
+@pytest.mark.parametrize("steps,K", [(10, 1), (7, 3), (0, 4)])
+def test_rollout_segmentations_match_oracle(steps, K):
+    """Every segment length, including one-step segments and no steps at all."""
+    shape, tau = (16, 16), 0.8
+    f = fields(shape, synthetic.BASE_SEED + 5)
+    rt_np = synthetic.target_bloch_field(shape, synthetic.BASE_SEED + 105)
+    h = make_handle(shape, tau=tau)
+    W0 = gpu_init(h, f)
+    L, gW, gtau = _loss_and_grad(h, W0, tau, steps, K, torch.from_numpy(rt_np).cuda())
+    lat, Wo = oracle_init(shape, f)
+    Lo, Lam0, dtau_o = adjoint.rollout_grad(lat, Wo, tau, steps, rt_np)
+    assert abs(L / Lo - 1) < 1e-12
+    assert normwise_rel_err(to_pauli_np(h, gW), pauli.pauli_from_matrix(Lam0) / 2.0) < 1e-11
+    if steps > 0:
+        assert abs(gtau / dtau_o - 1) < 1e-11
+    else:
+        assert gtau == 0.0
+
+
+def test_rollout_backward_twice():
+    """A second backward over the same graph (retain_graph) recomputes the last segment and agrees."""
+    shape, tau, steps, K = (16, 16), 0.8, 10, 4
+    f = fields(shape, synthetic.BASE_SEED + 5)
+    rt = torch.from_numpy(synthetic.target_bloch_field(shape, synthetic.BASE_SEED + 105)).cuda()
+    h = make_handle(shape, tau=tau)
+    W0 = gpu_init(h, f).requires_grad_(True)
+    tau_t = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+    loss = MLBMRollout.apply(W0, tau_t, h, steps, K, rt)
+    loss.backward(retain_graph=True)
+    g1, t1 = W0.grad.clone(), tau_t.grad.clone()
+    W0.grad, tau_t.grad = None, None
+    loss.backward()
+    assert torch.equal(W0.grad, g1)
+    assert tau_t.grad.item() == t1.item()
