@@ -11,7 +11,10 @@ the double-precision step.  Also reported: FP32 and FP16 scaled-deviation
 storage on the same workload, the fused kernel's average duration and HBM
 roofline fraction, the forward + adjoint time of the differentiable rollout
 (D2Q9 512^2, FP32, 200 steps, checkpoints every 20) next to the plain FP64
-forward, a device-copy bandwidth, and the CPU oracle on a bounded sample.
+forward, one D3Q19 128^3 adjoint step in FP64 and FP32, the magnetic-field
+and variant steps, the launch-bound Riemann run eager and as a HIP graph, the
+library's plain device copy (the achievable-bandwidth reference), the error
+against the stored FP64 oracle run, and the CPU oracle on a bounded sample.
 
 With --sweep the line also carries "sweep": every step workload (D2Q9 64^2,
 512^2, 1024^2 shear; D3Q19 64^3, 128^3, 384^3) in each storage type it is
