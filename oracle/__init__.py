@@ -22,6 +22,8 @@ Modules
              the Fermi-Dirac parameters (Prop. 1, Eqs. WeqFD, WeqDiscr)
   adjoint    reverse-mode derivative of the step and of the spin loss
   magnetic   the collision with an external magnetic field (Sec. 5)
+  variants   the isothermal equilibrium (Sec. 3.1) and the positivity-limited
+             relaxation rate (Sec. 3.3)
   euler      the exact solution of the Riemann problem of the Euler
              equations (Eq. Euler), the reference of the Riemann workload
   pauli      conversion between the matrix form and Pauli coefficients
