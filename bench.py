@@ -63,6 +63,8 @@ def parse():
                     help="storage type of the headline measurement (f64 is the benchmark; the others serve "
                          "per-precision profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-step", action="store_true",
+                    help="measure the D3Q19 128^3 adjoint step also with --skip-extras (for counter runs)")
     ap.add_argument("--sweep", action="store_true",
                     help="also measure every step workload in each storage type it is run in")
     ap.add_argument("--copy-probe", action="store_true",
@@ -449,14 +451,14 @@ def main():
         log("forward + adjoint rollout")
         extras["adjoint"] = measure_adjoint(args.warmup)
         log(f"  ratio {extras['adjoint']['ratio_to_f64_forward']:.2f}")
-        if args.workload == "d3q19_128":
-            log("adjoint step, D3Q19 128^3")
-            adj3 = {"workload": "D3Q19 128^3, one mlbm_adjoint_step", "f64_fused_forward_ms": r64["fused_kernel_ms"]}
-            for name, st in (("f64", mlbm.MLBM_STORE_F64), ("fp32", mlbm.MLBM_STORE_F32)):
-                adj3[name] = measure_adjoint_step(shape, tau, f, st)
-                adj3[name]["ratio_to_f64_forward_pass"] = adj3[name]["ms"] / r64["fused_kernel_ms"]
-                log(f"  {name}: {adj3[name]['ms'] * 1e3:.1f} us, {adj3[name]['GBps']:.0f} GB/s")
-            extras["adjoint"]["d3q19_128_step"] = adj3
+    if args.workload == "d3q19_128" and (args.adjoint_step or not args.skip_extras):
+        log("adjoint step, D3Q19 128^3")
+        adj3 = {"workload": "D3Q19 128^3, one mlbm_adjoint_step", "f64_fused_forward_ms": r64["fused_kernel_ms"]}
+        for name, st in (("f64", mlbm.MLBM_STORE_F64), ("fp32", mlbm.MLBM_STORE_F32)):
+            adj3[name] = measure_adjoint_step(shape, tau, f, st)
+            adj3[name]["ratio_to_f64_forward_pass"] = adj3[name]["ms"] / r64["fused_kernel_ms"]
+            log(f"  {name}: {adj3[name]['ms'] * 1e3:.1f} us, {adj3[name]['GBps']:.0f} GB/s")
+        extras.setdefault("adjoint", {})["d3q19_128_step"] = adj3
     if args.sweep:
         extras["sweep"] = sweep(args.warmup)
     if args.workload == "d3q19_128" and not args.skip_extras:
