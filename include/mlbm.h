@@ -66,8 +66,8 @@
  * Streams.  Every call that takes `stream` (a hipStream_t; NULL means the
  * null stream) enqueues its work asynchronously on that stream and returns.
  * The exceptions synchronise `stream` and say so: mlbm_init_equilibrium and
- * mlbm_init_chemical (read back status flags) and mlbm_moments when a host
- * output is requested.
+ * mlbm_init_chemical (read back status flags), mlbm_relaxation (host output)
+ * and mlbm_moments when a host output is requested.
  * A handle must not be used by two host threads at once; calls on one handle
  * on different streams must be ordered by the caller.
  *
