@@ -47,3 +47,42 @@ def test_captured_steps_replay_bitwise(shape, storage, field):
         torch.cuda.synchronize()
         assert torch.equal(Wg, We), f"replay {rep}"
         assert torch.isfinite(junk)
+
+
+@pytest.mark.parametrize("shape,n", [((37, 70), 5), ((13, 9, 11), 4)])
+def test_captured_checkpoint_segment_replay_bitwise(shape, n):
+    """A checkpointed segment as the rollout runs it, captured once: mlbm_step_states keeping the
+    states, then mlbm_adjoint_sweep over them (odd n adds its final device copy).  Every replay
+    matches the eager calls bit for bit, dL/domega included."""
+    print(f"graph segment {shape} n={n}", flush=True)
+    h = make_handle(shape, tau=0.9, storage=mlbm.MLBM_STORE_F64)
+    W0 = gpu_init(h, fields(shape, 14))
+    rng = np.random.default_rng(3)
+    lamN = torch.from_numpy(rng.standard_normal(tuple(W0.shape))).cuda()
+    bufs = {}
+    for tag in ("g", "e"):
+        bufs[tag] = dict(out=h.empty_field(), lam=h.empty_field(), tmp=h.empty_field(),
+                         states=torch.empty((n,) + tuple(W0.shape), dtype=W0.dtype, device="cuda"),
+                         dom=torch.zeros(1, dtype=torch.float64, device="cuda"))
+
+    def segment(b):
+        b["lam"].copy_(lamN)
+        b["dom"].zero_()
+        mlbm.mlbm_step_states(h, W0, b["out"], b["states"], n, nstates=n)
+        mlbm.mlbm_adjoint_sweep(h, W0, b["states"], n, b["lam"], b["tmp"], b["dom"])
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):                         # warm-up (sizes the library's reduction buffer)
+        segment(bufs["g"])
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        segment(bufs["g"])
+    for rep in range(3):
+        g.replay()
+        segment(bufs["e"])
+        torch.cuda.synchronize()
+        for key in ("out", "lam", "states", "dom"):
+            assert torch.equal(bufs["g"][key], bufs["e"][key]), (rep, key)
