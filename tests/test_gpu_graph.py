@@ -86,3 +86,38 @@ def test_captured_checkpoint_segment_replay_bitwise(shape, n):
         torch.cuda.synchronize()
         for key in ("out", "lam", "states", "dom"):
             assert torch.equal(bufs["g"][key], bufs["e"][key]), (rep, key)
+
+
+_FRESH_CAPTURE = r"""
+import sys
+sys.path.insert(0, sys.argv[1]); sys.path.insert(0, sys.argv[1] + "/tests")
+import torch
+from helpers import fields, gpu_init, make_handle
+from paper_1309_1656_amd import mlbm
+shape = (13, 9, 130)
+h = make_handle(shape, tau=0.9, storage=mlbm.MLBM_STORE_F64)
+W0 = gpu_init(h, fields(shape, 12))
+Wg, tg, We, te = W0.clone(), h.empty_field(), W0.clone(), h.empty_field()
+torch.cuda.synchronize()
+g = torch.cuda.CUDAGraph()
+with torch.cuda.graph(g):              # the first step launch of this process happens under capture
+    mlbm.mlbm_step(h, Wg, tg, 5)
+for rep in range(3):
+    g.replay()
+    mlbm.mlbm_step(h, We, te, 5)
+    torch.cuda.synchronize()
+    assert torch.equal(Wg, We), rep
+print("fresh capture ok")
+"""
+
+
+def test_first_launch_under_capture():
+    """In a new process the first mlbm_step call may come inside a capture: the launch-shape set-up
+    (occupancy queries for the LDS cap) enqueues nothing, so capture and replays still work."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, "-c", _FRESH_CAPTURE, root], capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert "fresh capture ok" in res.stdout
