@@ -405,8 +405,8 @@ def _cpu_model():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the design for spatial sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(spatial sharding by slabs is designed, not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1309_1656_amd import mlbm, synthetic
