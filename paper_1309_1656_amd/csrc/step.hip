@@ -199,13 +199,14 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
     } else {
         // q_i of the trace wave; with a field the same LDS is reused for the
         // exchange of the three Bloch channels (3 Q BX values).  The
-        // positivity variant also hands the Bloch channels to the trace wave.
+        // positivity variant shares all four channels and w_i P_i, and every
+        // wave bounds the rate for a quarter of the velocities.
         constexpr bool kIso = (VAR & kVarIso) != 0, kPos = (VAR & kVarPos) != 0;
         static_assert(VAR == 0 || FIELD == kFieldNone, "variants and the field are exclusive");
-        __shared__ C lds[(FIELD != kFieldNone ? 3 : (kPos ? 4 : 1)) * Q * BX];
+        __shared__ C lds[(FIELD != kFieldNone ? 3 : (kPos ? 5 : 1)) * Q * BX];
         __shared__ double rsh[VAR != 0 ? 4 : 1][BX];      // rho_k of the Bloch waves; tr rho
         __shared__ double esh[kIso ? 2 : 1][BX];          // isothermal: F_{d/2}(nu) per eigen-channel
-        __shared__ C omsh[kPos ? BX : 1];                 // per-cell relaxation rate
+        __shared__ C pmin[kPos ? 4 : 1][BX];              // positivity: each wave's bound on the rate
         C (*qs)[BX] = reinterpret_cast<C (*)[BX]>(lds);
         C a[Q];
         double rk = 0.0;
@@ -215,15 +216,13 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
             rk += static_cast<double>(a[i]);
         }
         if constexpr (VAR != 0) {
-            if (k > 0) {
-                rsh[k - 1][lx] = rk;
-                if constexpr (kPos) {
-                    C (*ab)[Q][BX] = reinterpret_cast<C (*)[Q][BX]>(lds + Q * BX);
+            if (k > 0) rsh[k - 1][lx] = rk;
+            else rsh[3][lx] = rk;
+            if constexpr (kPos) {
+                // channel k at ab[k - 1] (Bloch), the trace at ab[3]
+                C (*ab)[Q][BX] = reinterpret_cast<C (*)[Q][BX]>(lds + Q * BX);
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) ab[k - 1][i][lx] = a[i];
-                }
-            } else {
-                rsh[3][lx] = rk;
+                for (int i = 0; i < Q; ++i) ab[k > 0 ? k - 1 : 3][i][lx] = a[i];
             }
             __syncthreads();
             if constexpr (kIso) {
@@ -268,7 +267,6 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
             const C v1 = static_cast<C>(p.beta0 * p.xi * u1);
             const C v2 = static_cast<C>(p.beta0 * p.xi * u2);
             const C a3 = cst<C>(p.a3, p.a3f), a4 = cst<C>(p.a4, p.a4f);
-            C wP[kPos ? Q : 1];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 C cv = C(0);
@@ -277,34 +275,47 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
                 if (Lat<Q>::c(i, 2) == 1) cv += v2; else if (Lat<Q>::c(i, 2) == -1) cv -= v2;
                 C P = A + cv * (a3 + a4 * cv);
                 if (csq<Q>(i) == 1) P += B; else if (csq<Q>(i) == 2) P += C(2) * B;
-                if constexpr (kPos) wP[i] = static_cast<C>(p.w[i]) * P;
+                // positivity: qs holds w_i P_i (the equilibrium of population i is w_i P_i rho, Eq. WeqAlgo)
+                if constexpr (kPos) qs[i][lx] = static_cast<C>(p.w[i]) * P;
                 else qs[i][lx] = omw_of<C>(p, i) * P;
             }
-            if constexpr (kPos) {
-                // the equilibrium of population i is wP_i rho (Eq. WeqAlgo)
-                C (*ab)[Q][BX] = reinterpret_cast<C (*)[Q][BX]>(lds + Q * BX);
-                const C r0 = static_cast<C>(rk), r1 = static_cast<C>(rsh[0][lx]), r2 = static_cast<C>(rsh[1][lx]),
-                        r3 = static_cast<C>(rsh[2][lx]);
-                const C om = static_cast<C>(p.om);
-                C omc = om;
+        }
+        if constexpr (kPos) {
+            // the largest rate in [0, omega] keeping every population's smaller
+            // eigenvalue at or above min(0, its value): wave k bounds velocities
+            // i = k mod 4, and the cell's rate is the minimum of the four bounds
+            __syncthreads();
+            C (*ab)[Q][BX] = reinterpret_cast<C (*)[Q][BX]>(lds + Q * BX);
+            const C r0 = static_cast<C>(rsh[3][lx]), r1 = static_cast<C>(rsh[0][lx]),
+                    r2 = static_cast<C>(rsh[1][lx]), r3 = static_cast<C>(rsh[2][lx]);
+            const C om = static_cast<C>(p.om);
+            C m = om;
 #pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    omc = fmin(omc, psd_bound<C>(a[i], ab[0][i][lx], ab[1][i][lx], ab[2][i][lx], wP[i] * r0,
-                                                 wP[i] * r1, wP[i] * r2, wP[i] * r3, om));
-                omsh[lx] = omc;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) qs[i][lx] = omc * wP[i];
+            for (int i = 0; i < Q; ++i) {
+                if ((i & 3) == k) {
+                    const C wPi = qs[i][lx];
+                    m = fmin(m, psd_bound<C>(ab[3][i][lx], ab[0][i][lx], ab[1][i][lx], ab[2][i][lx], wPi * r0,
+                                             wPi * r1, wPi * r2, wPi * r3, om));
+                }
             }
+            pmin[k][lx] = m;
         }
         __syncthreads();
         // collision (Eq. CollisionStep) of this wave's channel
         const C r = static_cast<C>(rk);
-        C omm;
-        if constexpr (kPos) omm = C(1) - omsh[lx];
-        else omm = cst<C>(p.one_m_om, p.one_m_omf);
+        C omm, omc = C(0);
+        if constexpr (kPos) {
+            omc = fmin(fmin(pmin[0][lx], pmin[1][lx]), fmin(pmin[2][lx], pmin[3][lx]));
+            omm = C(1) - omc;
+        } else {
+            omm = cst<C>(p.one_m_om, p.one_m_omf);
+        }
         C S[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) S[i] = omm * a[i] + qs[i][lx] * r;
+        for (int i = 0; i < Q; ++i) {
+            if constexpr (kPos) S[i] = omm * a[i] + (omc * qs[i][lx]) * r;
+            else S[i] = omm * a[i] + qs[i][lx] * r;
+        }
         if constexpr (MODE == kF32) conserve<Q, C, !kIso>(S, a, k);
         if constexpr (FIELD != kFieldNone) {
             // magnetic precession of the Bloch components; it commutes with the
