@@ -160,11 +160,11 @@ def test_d3q19_384(storage):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("storage", [mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32])
+@pytest.mark.parametrize("storage", [mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32, mlbm.MLBM_STORE_F16DEV])
 def test_d3q19_512_large(storage):
     """D3Q19 512^3 (134M cells; FP64: two 81.6 GB fields), 3 steps: the largest grid
     here, past 2^32 field elements.  Conservation, and a sampled oracle step in FP32
-    (FP64 keeps no third field for it)."""
+    (FP64 keeps no third field for it; FP16 deviation has no sampled check)."""
     shape = (512, 512, 512)
     f = synthetic.macroscopic_fields(shape, B + 6, device="cuda")
     sampled = storage == mlbm.MLBM_STORE_F32
@@ -187,8 +187,10 @@ def test_d3q19_512_large(storage):
     assert nneg == 0
     if storage == mlbm.MLBM_STORE_F64:
         assert drift < 1e-13
-    else:
+    elif storage == mlbm.MLBM_STORE_F32:
         assert drift < 1e-9 and out["step"] < 1e-6
+    else:
+        assert drift < 1e-5          # half-precision quantisation of the deviations
     del W, scratch, Wb, h
     torch.cuda.empty_cache()
 
