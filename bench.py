@@ -137,7 +137,7 @@ def measure_step(shape, seed, tau, storage, steps, warmup, f, field=None, isothe
     info = h.info
     out = {
         "launch": {"block_x": info["launch_block_x"], "order": ["natural", "xcd_range", "interleave8"][info["launch_order"]],
-                   "blocks_per_cu": info["launch_blocks_per_cu"]},
+                   "blocks_per_cu": info["launch_blocks_per_cu"], "temporal_stores": info["launch_temporal_stores"]},
         "mlups": N * steps / (t_all * 1e-3) / 1e6,
         "ms_per_step": t_all / steps,
         "fused_kernel_ms": fused_ms,

@@ -123,6 +123,7 @@ typedef struct {
     double f16_scale;     /* S of MLBM_STORE_F16DEV (0 before initialisation) */
     double f16_ref[4][19];/* R_ki of MLBM_STORE_F16DEV                          */
     int launch_blocks_per_cu; /* step kernels: resident workgroups per CU (0: hardware limit) */
+    int launch_temporal_stores; /* step kernels: 1 temporal field writes, 0 streaming */
 } mlbm_info;
 
 /*
@@ -393,6 +394,17 @@ int mlbm_set_magnetic_field_map(mlbm_handle h, const double* mu_b);
  * Errors: MLBM_EINVAL.
  */
 int mlbm_set_launch(mlbm_handle h, int block_x, int order, int blocks_per_cu);
+
+/*
+ * mlbm_set_store_policy -- how the step passes write a field: -1 automatic
+ * (the default: temporal when one field holds at most 192 MiB, so that both
+ * fields of a pass can stay in the 256 MB last-level cache between passes;
+ * streaming above), 0 streaming (non-temporal) stores, 1 temporal stores.
+ * The stored values are the same either way; the magnetic-field and variant
+ * kernels always stream.  mlbm_get_info reports the policy in effect.
+ * Errors: MLBM_EINVAL (policy outside -1..1).
+ */
+int mlbm_set_store_policy(mlbm_handle h, int policy);
 
 /*
  * mlbm_adjoint_segment -- the adjoint of nsteps >= 0 consecutive steps in one

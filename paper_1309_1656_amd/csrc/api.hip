@@ -257,10 +257,14 @@ int mlbm_get_info(mlbm_handle h, mlbm_info* info) {
     // as the launcher applies it: the variant kernels exist for 64-cell blocks,
     // and the field and variant kernels run without the occupancy cap
     if (h->kp.variant != 0) lc.bx = 64;
-    if (h->kp.variant != 0 || h->kp.field_mode != kFieldNone) lc.cap = 0;
+    if (h->kp.variant != 0 || h->kp.field_mode != kFieldNone) {
+        lc.cap = 0;
+        lc.stores = 0;
+    }
     info->launch_block_x = lc.bx;
     info->launch_order = lc.order;
     info->launch_blocks_per_cu = lc.cap;
+    info->launch_temporal_stores = lc.stores;
     info->f16_scale = h->f16_scale;
     for (int k = 0; k < 4; ++k)
         for (int i = 0; i < h->Q; ++i) info->f16_ref[k][i] = h->f16_ref[k][i];
@@ -356,6 +360,13 @@ int mlbm_set_launch(mlbm_handle h, int block_x, int order, int blocks_per_cu) {
     h->launch.bx = block_x;
     h->launch.order = order;
     h->launch.cap = blocks_per_cu;
+    return ok();
+}
+
+int mlbm_set_store_policy(mlbm_handle h, int policy) {
+    if (int e = check_handle(h)) return e;
+    if (policy < -1 || policy > 1) return fail(MLBM_EINVAL, "store policy must be -1, 0 or 1");
+    h->launch.stores = policy;
     return ok();
 }
 

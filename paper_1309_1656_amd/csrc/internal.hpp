@@ -16,6 +16,7 @@ struct LaunchCfg {
     int bx = 0;
     int order = -1;
     int cap = -1;      // workgroups resident per CU: -1 automatic, 0 hardware limit, > 0 at most that many
+    int stores = -1;   // field writes: -1 automatic, 0 streaming (non-temporal), 1 temporal
 };
 LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want);
 

@@ -24,7 +24,7 @@ EXPORTS = (
     "mlbm_init_equilibrium", "mlbm_step", "mlbm_collide", "mlbm_stream", "mlbm_moments", "mlbm_spin_loss",
     "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_step_states", "mlbm_adjoint_sweep", "mlbm_set_f16_reference", "mlbm_set_launch",
     "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_init_chemical", "mlbm_relaxation", "mlbm_set_positivity",
-    "mlbm_device_copy", "mlbm_last_error",
+    "mlbm_device_copy", "mlbm_set_store_policy", "mlbm_last_error",
 )
 
 
@@ -45,7 +45,7 @@ class Info(ctypes.Structure):
         ("a2_b", ctypes.c_double), ("a3", ctypes.c_double), ("a4", ctypes.c_double), ("a5", ctypes.c_double),
         ("launch_block_x", ctypes.c_int), ("launch_order", ctypes.c_int),
         ("f16_scale", ctypes.c_double), ("f16_ref", (ctypes.c_double * 19) * 4),
-        ("launch_blocks_per_cu", ctypes.c_int),
+        ("launch_blocks_per_cu", ctypes.c_int), ("launch_temporal_stores", ctypes.c_int),
     ]
 
 
@@ -86,6 +86,7 @@ def load_library(path=LIB_PATH):
         "mlbm_relaxation": ([vp, vp, dp, vp], ctypes.c_int),
         "mlbm_set_positivity": ([vp, ctypes.c_int], ctypes.c_int),
         "mlbm_device_copy": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+        "mlbm_set_store_policy": ([vp, ctypes.c_int], ctypes.c_int),
         "mlbm_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -368,6 +369,12 @@ def mlbm_set_positivity(h, on):
 
 def mlbm_set_launch(h, block_x=0, order=MLBM_ORDER_AUTO, blocks_per_cu=-1):
     _check(load_library().mlbm_set_launch(h.ptr, int(block_x), int(order), int(blocks_per_cu)))
+    mlbm_get_info(h)
+
+
+def mlbm_set_store_policy(h, policy=-1):
+    """-1 automatic, 0 streaming (non-temporal) field writes, 1 temporal."""
+    _check(load_library().mlbm_set_store_policy(h.ptr, int(policy)))
     mlbm_get_info(h)
 
 

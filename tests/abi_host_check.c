@@ -96,6 +96,9 @@ int main(void) {
     EXPECT(mlbm_adjoint_sweep(h, p1, NULL, 0, p2, (void*)0x3000, NULL, NULL), MLBM_OK);
     EXPECT(mlbm_adjoint_sweep(h, p1, NULL, 2, p2, (void*)0x3000, NULL, NULL), MLBM_EINVAL);
     EXPECT(mlbm_adjoint_sweep(h16, p1, p2, 2, (void*)0x3000, (void*)0x4000, NULL, NULL), MLBM_EINVAL);
+    EXPECT(mlbm_set_store_policy(h, 1), MLBM_OK);
+    EXPECT(mlbm_set_store_policy(h, 3), MLBM_EINVAL);
+    EXPECT(mlbm_set_store_policy(h, -1), MLBM_OK);
     EXPECT(mlbm_device_copy(NULL, p2, 64, NULL), MLBM_EINVAL);
     EXPECT(mlbm_device_copy(p1, p2, 24, NULL), MLBM_EINVAL);                /* not a multiple of 16 */
     EXPECT(mlbm_device_copy((void*)0x1008, p2, 64, NULL), MLBM_EINVAL);     /* misaligned */

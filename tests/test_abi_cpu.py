@@ -226,3 +226,25 @@ def test_step_states_and_sweep_validation():
     mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_ISOTHERMAL)
     assert lib.mlbm_adjoint_sweep(h.ptr, src, st, 3, lam, tmp, None, None) == mlbm.MLBM_EINVAL
     assert "direct equilibrium" in mlbm.mlbm_last_error()
+
+
+def test_store_policy():
+    """Automatic store policy: temporal writes up to 192 MiB per field, streaming above; the
+    field and variant kernels always stream; the setter validates its argument."""
+    cases = [(19, (128, 128, 128), mlbm.MLBM_STORE_F64, 0), (19, (64, 64, 64), mlbm.MLBM_STORE_F64, 1),
+             (9, (512, 512, 1), mlbm.MLBM_STORE_F32, 1), (9, (1024, 1024, 1), mlbm.MLBM_STORE_F64, 0),
+             (9, (1024, 1024, 1), mlbm.MLBM_STORE_F32, 1), (19, (128, 128, 128), mlbm.MLBM_STORE_F16DEV, 0)]
+    for Q, dims, st, want in cases:
+        h = mlbm.mlbm_create(Q, dims, 0.8, 1.0, st)
+        assert h.info["launch_temporal_stores"] == want, (Q, dims, st)
+    h = mlbm.mlbm_create(19, (64, 64, 64), 0.8, 1.0, mlbm.MLBM_STORE_F64)
+    mlbm.mlbm_set_store_policy(h, 0)
+    assert h.info["launch_temporal_stores"] == 0
+    mlbm.mlbm_set_store_policy(h, 1)
+    assert h.info["launch_temporal_stores"] == 1
+    mlbm.mlbm_set_magnetic_field(h, [0.0, 0.0, 0.1])
+    assert h.info["launch_temporal_stores"] == 0
+    for bad in (-2, 2):
+        with pytest.raises(mlbm.MlbmError) as e:
+            mlbm.mlbm_set_store_policy(h, bad)
+        assert e.value.code == mlbm.MLBM_EINVAL

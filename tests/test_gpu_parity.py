@@ -247,24 +247,27 @@ def test_resume_is_bitwise():
 @pytest.mark.parametrize("shape", [(37, 70), (13, 9, 130), (5, 6, 1)])
 @pytest.mark.parametrize("storage", [mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32, mlbm.MLBM_STORE_F16DEV])
 def test_launch_shapes_give_identical_results(shape, storage):
-    """Every block width, XCD order and occupancy cap computes the same field, bit
-    for bit (the shapes only reorder independent cells); ragged rows included."""
+    """Every block width, XCD order, occupancy cap and store policy computes the same
+    field, bit for bit (the shapes only reorder independent cells); ragged rows included."""
     _flush(f"launch shapes {shape} storage={storage}")
     f = fields(shape, 19)
     h = make_handle(shape, storage=storage)
     W0 = gpu_init(h, f)
     ref = None
-    for bx in (64, 128):
-        for order in (mlbm.MLBM_ORDER_NATURAL, mlbm.MLBM_ORDER_XCD_RANGE, mlbm.MLBM_ORDER_INTERLEAVE8):
-            for cap in (0, 2):
-                mlbm.mlbm_set_launch(h, bx, order, cap)
-                W = W0.clone()
-                mlbm.mlbm_step(h, W, h.empty_field(), 3)
-                torch.cuda.synchronize()
-                if ref is None:
-                    ref = W
-                else:
-                    assert torch.equal(W, ref), (bx, order, cap)
+    for stores in (0, 1):
+        mlbm.mlbm_set_store_policy(h, stores)
+        assert h.info["launch_temporal_stores"] == stores
+        for bx in (64, 128):
+            for order in (mlbm.MLBM_ORDER_NATURAL, mlbm.MLBM_ORDER_XCD_RANGE, mlbm.MLBM_ORDER_INTERLEAVE8):
+                for cap in (0, 2):
+                    mlbm.mlbm_set_launch(h, bx, order, cap)
+                    W = W0.clone()
+                    mlbm.mlbm_step(h, W, h.empty_field(), 3)
+                    torch.cuda.synchronize()
+                    if ref is None:
+                        ref = W
+                    else:
+                        assert torch.equal(W, ref), (stores, bx, order, cap)
 
 
 @pytest.mark.parametrize("shape", [(37, 70), (13, 9, 130)])
