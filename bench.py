@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, AMD published peak
 TRAFFIC_FILES = {"f64": os.path.join(ROOT, "profiles", "k_step_d3q19_128_traffic.json"),
                  "fp32": os.path.join(ROOT, "profiles", "k_step_d3q19_128_fp32_traffic.json"),
                  "f16dev": os.path.join(ROOT, "profiles", "k_step_d3q19_128_f16dev_traffic.json")}
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1309_1656_amd", "csrc", f) for f in ("step.hip", "common.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1309_1656_amd", "csrc", f) for f in ("step.hip", "common.hpp", "block_order.hpp")]
 
 
 # step workloads (names in paper_1309_1656_amd.synthetic.WORKLOADS) and the storage types the sweep runs them in
@@ -244,11 +244,23 @@ GOLDEN_128 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "
                           "oracle_d3q19_128_tau0.8_500.npz")
 
 
+def f16dev_decode(h, vals):
+    """Decoded populations of F16 scaled-deviation values [4, Q, ...] (the storage format of
+    include/mlbm.h: a = R_ki + s_i h, s_i the power of two nearest w_i S, summed in float)."""
+    info = h.info
+    x = np.log2(np.asarray(info["w"]) * info["f16_scale"])
+    sc = np.ldexp(1.0, (np.sign(x) * np.floor(np.abs(x) + 0.5)).astype(np.int64)).astype(np.float32)
+    extra = vals.ndim - 2
+    ref = np.asarray(info["f16_ref"], dtype=np.float32).reshape((4, -1) + (1,) * extra)
+    return (ref + sc.reshape((1, -1) + (1,) * extra) * vals.astype(np.float32)).astype(np.float64)
+
+
 def measure_accuracy(f, storage):
     """Error of the benchmark workload (D3Q19 128^3, tau 0.8, 500 steps from the
     same initial state) against the stored FP64 oracle run: normwise over the
     1 024 stored cells, max over Pauli components of max|d a_k| / max|a_k|.
-    F16 deviation storage is compared on the cell density matrices."""
+    F16 deviation storage is compared population by population (decoded) and
+    on the cell density matrices."""
     import torch
     from paper_1309_1656_amd import mlbm
     if not os.path.exists(GOLDEN_128):
@@ -260,14 +272,18 @@ def measure_accuracy(f, storage):
     mlbm.mlbm_init_equilibrium(h, W, *device_inputs(h, f))
     mlbm.mlbm_step(h, W, h.empty_field(), int(g["meta"][1]))
     idx = tuple(torch.from_numpy(c).cuda() for c in np.unravel_index(g["cells"], shape))
+    sel = h.pauli_view(W)[(slice(None), slice(None)) + idx]
     if storage == mlbm.MLBM_STORE_F16DEV:
+        got = f16dev_decode(h, sel.cpu().numpy())
+        pop = max(float(np.abs(got[k] - g["values"][k]).max() / g["maxabs"][k]) for k in range(4))
         rho4 = torch.empty((4,) + shape, dtype=torch.float64, device="cuda")
         mlbm.mlbm_moments(h, W, rho4=rho4)
-        got = rho4[(slice(None),) + idx].cpu().numpy()
+        got_rho = rho4[(slice(None),) + idx].cpu().numpy()
         ref = g["values"].sum(axis=1)
-        err = max(float(np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max()) for k in range(4))
+        rho = max(float(np.abs(got_rho[k] - ref[k]).max() / np.abs(ref[k]).max()) for k in range(4))
+        err = {"populations": pop, "rho": rho}
     else:
-        got = h.pauli_view(W)[(slice(None), slice(None)) + idx].to(torch.float64).cpu().numpy()
+        got = sel.to(torch.float64).cpu().numpy()
         err = max(float(np.abs(got[k] - g["values"][k]).max() / g["maxabs"][k]) for k in range(4))
     h.destroy()
     return err
@@ -464,7 +480,8 @@ def main():
     if args.workload == "d3q19_128" and not args.skip_extras:
         log("accuracy against the stored FP64 oracle run")
         acc = {"reference": "FP64 oracle, same initial state, tau 0.8, 500 steps; 1024 stored cells; "
-                            "max over Pauli components k of max|d a_k| / max|a_k| (FP16: of the density matrix)"}
+                            "max over Pauli components k of max|d a_k| / max|a_k| (FP16: of the decoded "
+                            "populations and of the cell density matrices)"}
         for name, st in (("f64", mlbm.MLBM_STORE_F64), ("fp32", mlbm.MLBM_STORE_F32),
                          ("f16dev", mlbm.MLBM_STORE_F16DEV)):
             acc[name] = measure_accuracy(f, st)

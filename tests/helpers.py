@@ -1,7 +1,10 @@
-"""Shared helpers of the GPU tests: input marshalling and error metrics.
+"""Shared helpers of the GPU tests: input marshalling, error metrics and the
+decoding of the F16 scaled-deviation storage format.
 
 No arithmetic of the method lives here: inputs come from
-paper_1309_1656_amd.synthetic, expected values from the oracle.
+paper_1309_1656_amd.synthetic, expected values from the oracle.  The F16
+decoding follows the storage format as include/mlbm.h documents it (a field's
+layout, not a step of the method), written independently of the kernels.
 """
 import numpy as np
 import torch
@@ -74,3 +77,35 @@ def normwise_rel_err(got, ref):
 
 def fields(shape, seed):
     return synthetic.macroscopic_fields(shape, seed)
+
+
+def f16dev_scales(h):
+    """Per-velocity scale s_i of the F16 scaled-deviation codec as the library sets it: the power of
+    two nearest w_i S (rounding half away from zero on log2), with S = info["f16_scale"]."""
+    info = h.info
+    x = np.log2(np.asarray(info["w"]) * info["f16_scale"])
+    e = (np.sign(x) * np.floor(np.abs(x) + 0.5)).astype(np.int64)
+    return np.ldexp(1.0, e)
+
+
+def decode_f16dev(h, t):
+    """Decoded populations [4, Q, *grid] (float64) of an F16 scaled-deviation field, by the codec that
+    include/mlbm.h documents: a = R_ki + s_i h, with R_ki = info["f16_ref"] held in float and the sum
+    rounded to float, as the kernels decode before they compute."""
+    hv = h.pauli_view(t.detach()).cpu().numpy().astype(np.float32)          # [4, Q, *grid] half -> float
+    bshape = (1, -1) + (1,) * (hv.ndim - 2)
+    ref = np.asarray(h.info["f16_ref"], dtype=np.float32).reshape((4, -1) + (1,) * (hv.ndim - 2))
+    sc = f16dev_scales(h).astype(np.float32).reshape(bshape)
+    return (ref + sc * hv).astype(np.float64)
+
+
+def f16dev_rounding_bound(h, expect):
+    """Largest error that encoding `expect` ([4, Q, ...] decoded values) can leave: half a unit in the
+    last place of the half-precision deviation (a - R_ki)/s_i, times s_i, elementwise; normal and
+    subnormal halves alike (the subnormal spacing is 2^-24)."""
+    extra = expect.ndim - 2
+    ref = np.asarray(h.info["f16_ref"], dtype=np.float64).reshape((4, -1) + (1,) * extra)
+    sc = f16dev_scales(h).reshape((1, -1) + (1,) * extra)
+    dev = np.abs((expect - ref) / sc)
+    ex = np.floor(np.log2(np.maximum(dev, 2.0 ** -14)))
+    return 0.5 * np.ldexp(1.0, (ex - 10).astype(np.int64)) * sc
