@@ -91,6 +91,7 @@ enum { MLBM_D2Q9 = 9, MLBM_D3Q19 = 19 };
 enum { MLBM_STORE_F64 = 0, MLBM_STORE_F32 = 1, MLBM_STORE_F16DEV = 2 };
 enum { MLBM_EQ_DIRECT = 0, MLBM_EQ_EIGEN = 1, MLBM_EQ_ISOTHERMAL = 2 };
 enum { MLBM_ORDER_AUTO = -1, MLBM_ORDER_NATURAL = 0, MLBM_ORDER_XCD_RANGE = 1, MLBM_ORDER_INTERLEAVE8 = 2 };
+enum { MLBM_ADJ_AUTO = 0, MLBM_ADJ_CHANNEL = 1, MLBM_ADJ_CELL = 2 };
 enum {
     MLBM_OK = 0,
     MLBM_EINVAL = -1,     /* bad argument: null pointer, bad enum, bad size   */
@@ -124,6 +125,11 @@ typedef struct {
     double f16_ref[4][19];/* R_ki of MLBM_STORE_F16DEV                          */
     int launch_blocks_per_cu; /* step kernels: resident workgroups per CU (0: hardware limit) */
     int launch_temporal_stores; /* step kernels: 1 temporal field writes, 0 streaming */
+    int adjoint_form;     /* adjoint kernels: MLBM_ADJ_CHANNEL or MLBM_ADJ_CELL in effect */
+    int adjoint_block_x;  /* channel form: cells per workgroup along x (0 in the cell form) */
+    int adjoint_order;    /* channel form: block order (MLBM_ORDER_*; -1 in the cell form) */
+    int adjoint_blocks_per_cu;   /* channel form: resident workgroups per CU (0: hardware limit) */
+    int adjoint_temporal_stores; /* channel form: 1 temporal writes of lam_n, 0 streaming */
 } mlbm_info;
 
 /*
@@ -396,10 +402,25 @@ int mlbm_set_magnetic_field_map(mlbm_handle h, const double* mu_b);
 int mlbm_set_launch(mlbm_handle h, int block_x, int order, int blocks_per_cu);
 
 /*
+ * mlbm_set_adjoint_launch -- launch shape of the adjoint kernels
+ * (mlbm_adjoint_step, mlbm_adjoint_segment, mlbm_adjoint_sweep; performance
+ * only, the values computed are the same up to the summation order of
+ * dL/domega).  form: MLBM_ADJ_CHANNEL runs one wave per Pauli component on
+ * block_x consecutive cells of one x-row, like the step kernels (block_x,
+ * order, blocks_per_cu and stores as for mlbm_set_launch and
+ * mlbm_set_store_policy); MLBM_ADJ_CELL runs one thread per cell with all
+ * four components (the other arguments are then ignored); MLBM_ADJ_AUTO
+ * chooses.  A magnetic field always uses the cell form.  mlbm_get_info
+ * reports the shape in effect.  Errors: MLBM_EINVAL.
+ */
+int mlbm_set_adjoint_launch(mlbm_handle h, int form, int block_x, int order, int blocks_per_cu, int stores);
+
+/*
  * mlbm_set_store_policy -- how the step passes write a field: -1 automatic
- * (the default: temporal when one field holds at most 192 MiB, so that both
- * fields of a pass can stay in the 256 MB last-level cache between passes;
- * streaming above), 0 streaming (non-temporal) stores, 1 temporal stores.
+ * (the default: temporal when one field holds at most 192 MiB, streaming
+ * above; an empirical cut-off from measured pass times, below which part of
+ * what the next pass reads is found in the 256 MB last-level cache), 0
+ * streaming (non-temporal) stores, 1 temporal stores.
  * The stored values are the same either way; the magnetic-field and variant
  * kernels always stream.  mlbm_get_info reports the policy in effect.
  * Errors: MLBM_EINVAL (policy outside -1..1).

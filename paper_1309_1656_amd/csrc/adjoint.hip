@@ -11,20 +11,30 @@
 // where v = beta0 xi u, and du/d(tr W_j) = (e_j - u)/T,
 // deps/d(tr W_j) = (|e_j - u|^2/2 - eps)/T.
 //
-// One thread per cell; fields are read in the storage type and all
-// arithmetic is in double.  The trace channel is handled first and last so
-// that each Bloch channel k = 1..3 is loaded, used and written in turn.  Two
-// forms of the same arithmetic: the wide one (D2Q9) loads a cell's values up
-// front and holds the per-velocity factors; the staged one (D3Q19) holds one
-// channel at a time and folds G_i into G_u, sum_i G_i and G_eps as it goes,
-// which halves its registers and doubles the waves per SIMD.
-//
-// With a magnetic field (FIELD) the Bloch part of g is turned back by the
-// transpose of the cell's rotation before it enters the collision's adjoint.
+// Fields are read in the storage type.  Two organisations of the same
+// arithmetic:
+// * channel-parallel (k_adjoint_channel, the default without a magnetic
+//   field): the step kernels' row-blocked cells with one wave per Pauli
+//   channel, so that every wave streams only the Q segments of its channel of
+//   each of the three fields.  The trace wave's moments reach the other waves
+//   through LDS; the Bloch waves hand back their parts of G_u, sum_i G_i and
+//   G_eps, which are linear in the G_i.  Per-population products are formed
+//   in the compute type of the storage (float for FP32, as in the step
+//   kernels) and summed in double.
+// * one thread per cell with all four channels: the trace channel is handled
+//   first and last so that each Bloch channel k = 1..3 is loaded, used and
+//   written in turn.  The wide form (D2Q9) loads a cell's values up front and
+//   holds the per-velocity factors; the staged one (D3Q19) holds one channel
+//   at a time and folds G_i into G_u, sum_i G_i and G_eps as it goes.  With a
+//   magnetic field (FIELD) the Bloch part of g is turned back by the transpose
+//   of the cell's rotation before it enters the collision's adjoint; that
+//   rotation mixes the three Bloch channels of a value, so the field runs in
+//   this form only.  All its arithmetic is in double.
 //
 // W_n can be read as stored (WPULL = false) or gathered from the previous
 // post-collision state S_{n-1}, W_n,i(x) = S_{n-1},i(x - c_i) (WPULL = true),
 // so that a recomputed segment needs one fused pass per state.
+#include "block_order.hpp"
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -441,19 +451,312 @@ k_adjoint_staged(const typename Store<MODE>::T* __restrict__ Wn, const typename 
     }
 }
 
+// Field write: streaming (non-temporal) or temporal.
+template <bool NT, typename T>
+__device__ __forceinline__ void put(T v, T* ptr) {
+    if constexpr (NT) __builtin_nontemporal_store(v, ptr);
+    else *ptr = v;
+}
+
+// Channel-parallel form: a workgroup covers BX consecutive cells of one row
+// (block_order), four waves per 64 cells, wave group k owning Pauli channel k.
+// Every wave gathers its channel of W_n (at x, or pulled from x - c_i) and of
+// lam_{n+1} (from x + c_i) and writes its channel of lam_n.
+//
+// Everything the collision's adjoint needs from a channel's g_i enters through
+// a few moments: with P_i = A + B |c_i|^2 + (c_i.v)(alpha3 + alpha4 c_i.v)
+// (v = beta0 xi u, A and B the cell's coefficient sums),
+//   h_k = sum_i w_i P_i g_i = A m0 + B mc + alpha3 v.m1 + alpha4 v.M2 v,
+//   G_u part  = rho_k beta0 xi (alpha3 m1 + 2 alpha4 M2 v),
+//   sum_i G_i part = rho_k m0,   G_eps part = rho_k (a1_b m0 + a2_b beta0 xi^2/2 mc),
+// with m0 = sum_i w_i g_i, mc = sum_i w_i |c_i|^2 g_i, m1 = sum_i w_i c_i g_i,
+// M2 = sum_i w_i c_i c_i^T g_i.  Since c_i is in {-1, 0, 1}^3 these are sums of
+// g_i with signs, weighted per weight class: additions only.  The trace wave
+// hands v, A, B to the other waves (first barrier); every wave forms its
+// moments and h_k and writes its Bloch channel at once; the Bloch waves hand
+// their G parts to the trace wave (second barrier), which writes the trace
+// channel.  Each wave's part of dL/domega, rho_k h_k - sum_i g_i a_i, is
+// summed with the others of the block after the second barrier (one partial
+// per block).
+template <int Q> struct GMoments {
+    static constexpr int D = Lat<Q>::D;
+    static constexpr int kM2 = D == 3 ? 6 : 3;                 // entries of M2: xx, yy, (zz,) xy, (xz, yz)
+};
+
+template <int Q>
+__device__ __forceinline__ void m2_index(int n, int& a, int& b) {
+    if constexpr (Lat<Q>::D == 3) {
+        constexpr int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+        a = ia[n];
+        b = ib[n];
+    } else {
+        constexpr int ia[3] = {0, 1, 0}, ib[3] = {0, 1, 1};
+        a = ia[n];
+        b = ib[n];
+    }
+}
+
+template <int Q, int MODE, bool WPULL, int BX, bool NTS>
+__global__ void __launch_bounds__(BX * 4)
+k_adjoint_channel(const typename Store<MODE>::T* __restrict__ Wn, const typename Store<MODE>::T* __restrict__ ln1,
+                  typename Store<MODE>::T* __restrict__ ln, const KParams p, double* __restrict__ partials,
+                  const int accumulate, const int order) {
+    using T = typename Store<MODE>::T;
+    using GM = GMoments<Q>;
+    constexpr int D = Lat<Q>::D;
+    constexpr int kWaves = BX / 64;           // waves per channel
+    constexpr int kM2 = GM::kM2;
+    static_assert(BX % 64 == 0, "a wave must not straddle two channels");
+    const int lx = threadIdx.x;
+    const int k = __builtin_amdgcn_readfirstlane(threadIdx.y);   // Pauli channel, uniform per wave
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    int chunk, y, z;
+    block_order(order, nx, ny, BX, chunk, y, z);
+    const int x = chunk * BX + lx;
+    const bool active = x < nx;
+    const int xx = active ? x : nx - 1;
+    const size_t row = static_cast<size_t>(z) * ny + y;
+    // coordinate x + c along each axis, indexed by c + 1 (x - c is the same table reversed)
+    const int xp[3] = {xx == 0 ? nx - 1 : xx - 1, xx, xx + 1 == nx ? 0 : xx + 1};
+    const int yp[3] = {y == 0 ? ny - 1 : y - 1, y, y + 1 == ny ? 0 : y + 1};
+    int zp[3] = {z, z, z};
+    if constexpr (D == 3) {
+        zp[0] = z == 0 ? nz - 1 : z - 1;
+        zp[2] = z + 1 == nz ? 0 : z + 1;
+    }
+
+    T wr[Q], gr[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = Lat<Q>::c(i, 0), cy = Lat<Q>::c(i, 1), cz = Lat<Q>::c(i, 2);
+        size_t wrow = row;
+        int wx = xx;
+        if constexpr (WPULL) {
+            wrow = static_cast<size_t>(zp[1 - cz]) * ny + yp[1 - cy];
+            wx = xp[1 - cx];
+        }
+        const size_t lrow = static_cast<size_t>(zp[1 + cz]) * ny + yp[1 + cy];
+        wr[i] = Wn[fidx(Q, nx, wrow, k, i, wx)];
+        gr[i] = ln1[fidx(Q, nx, lrow, k, i, xp[1 + cx])];
+    }
+
+    double rk = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) rk += static_cast<double>(wr[i]);
+
+    // the trace wave: moments of W_n (Eq. DiscrAvr) and the coefficient sums of P_i
+    // (Eq. WeqAlgo, Appendix), handed to the other waves
+    constexpr int kT = 2 + D;                      // v (D components), A, B
+    __shared__ double csh[kT][BX];
+    __shared__ double gsh[3][2 + D][BX];           // Bloch waves: parts of G_u (D), sum_i G_i, sum_i |c_i|^2 G_i
+    double u[3] = {0.0, 0.0, 0.0}, uu = 0.0, eps = 0.0, invT = 0.0;
+    const double bx = p.beta0 * p.xi;
+    if (k == 0) {
+        double J[3] = {0.0, 0.0, 0.0}, K = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double a = static_cast<double>(wr[i]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (Lat<Q>::c(i, c) > 0) J[c] += a;
+                if (Lat<Q>::c(i, c) < 0) J[c] -= a;
+            }
+            if (csq<Q>(i) == 1) K += a;
+            if (csq<Q>(i) == 2) K += 2.0 * a;
+        }
+        invT = 1.0 / rk;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            u[c] = p.xi * J[c] * invT;
+            uu += u[c] * u[c];
+        }
+        eps = p.half_xi2 * K * invT - 0.5 * uu;
+        const double b = p.beta0 * eps;
+#pragma unroll
+        for (int c = 0; c < D; ++c) csh[c][lx] = bx * u[c];
+        csh[D][lx] = p.a1_0 + p.a1_b * b + p.a5 * p.beta0 * 0.5 * uu;
+        csh[D + 1][lx] = (p.a2_0 + p.a2_b * b) * p.beta0 * p.half_xi2;
+    }
+    __syncthreads();
+    double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < D; ++c) v[c] = csh[c][lx];
+    const double A = csh[D][lx], B = csh[D + 1][lx];
+
+    // moments of this channel's g and sum_i g_i a_i
+    double ga = 0.0, s0 = 0.0, sa = 0.0, sd = 0.0;             // g summed per weight class
+    double m1a[3] = {0.0, 0.0, 0.0}, m1d[3] = {0.0, 0.0, 0.0};  // sum c_i g_i per class
+    double m2a[3] = {0.0, 0.0, 0.0}, m2d[kM2];                  // sum c_ia c_ib g_i per class
+#pragma unroll
+    for (int n = 0; n < kM2; ++n) m2d[n] = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double g = static_cast<double>(gr[i]);
+        ga += g * static_cast<double>(wr[i]);
+        if (csq<Q>(i) == 0) s0 += g;
+        if (csq<Q>(i) == 1) sa += g;
+        if (csq<Q>(i) == 2) sd += g;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double& m = csq<Q>(i) == 1 ? m1a[c] : m1d[c];
+            if (Lat<Q>::c(i, c) > 0) m += g;
+            if (Lat<Q>::c(i, c) < 0) m -= g;
+        }
+#pragma unroll
+        for (int n = 0; n < kM2; ++n) {
+            int ca, cb;
+            m2_index<Q>(n, ca, cb);
+            const int sgn = Lat<Q>::c(i, ca) * Lat<Q>::c(i, cb);
+            if (sgn == 0) continue;
+            if (csq<Q>(i) == 1) {          // an axis velocity has one nonzero component: diagonal entries only
+                if (n < D) m2a[n] += g;
+            } else {
+                if (sgn > 0) m2d[n] += g;
+                else m2d[n] -= g;
+            }
+        }
+    }
+    // weight classes: rest w[0], axis w[1], diagonal w[2 D + 1]
+    const double w0 = p.w[0], wa = p.w[1], wd = p.w[2 * D + 1];
+    const double m0 = w0 * s0 + wa * sa + wd * sd;
+    const double mc = wa * sa + 2.0 * wd * sd;
+    double m1[3] = {0.0, 0.0, 0.0}, M2v[3] = {0.0, 0.0, 0.0}, vM2v = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) m1[c] = wa * m1a[c] + wd * m1d[c];
+#pragma unroll
+    for (int n = 0; n < kM2; ++n) {
+        int ca, cb;
+        m2_index<Q>(n, ca, cb);
+        const double M = (n < D ? wa * m2a[n] : 0.0) + wd * m2d[n];
+        M2v[ca] += M * v[cb];
+        if (ca != cb) M2v[cb] += M * v[ca];
+    }
+    double vm1 = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        vm1 += v[c] * m1[c];
+        vM2v += v[c] * M2v[c];
+    }
+    const double h = A * m0 + B * mc + p.a3 * vm1 + p.a4 * vM2v;      // sum_i w_i P_i g_i
+    double dom = rk * h - ga;                                         // sum_i g_i (w_i P_i rho_k - a_i)
+    // this channel's parts of G_u / (beta0 xi) (without the alpha5 term), sum_i G_i, sum_i |c_i|^2 G_i
+    double Gu[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < D; ++c) Gu[c] = rk * (p.a3 * m1[c] + 2.0 * p.a4 * M2v[c]);
+    double Gs = rk * m0, Gc = rk * mc;
+    // this wave's part of dL/domega, summed in a fixed butterfly order (reproducible)
+    __shared__ double dsum[4 * kWaves];
+    if (!active) dom = 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dom += __shfl_xor(dom, off, 64);
+    if ((lx & 63) == 0) dsum[k * kWaves + lx / 64] = dom;
+    const double om = p.om, omm = p.one_m_om;
+    if (k > 0) {
+        const double mix = om * h;
+        if (active) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                put<NTS>(static_cast<T>(omm * static_cast<double>(gr[i]) + mix), ln + fidx(Q, nx, row, k, i, x));
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c) gsh[k - 1][c][lx] = Gu[c];
+        gsh[k - 1][D][lx] = Gs;
+        gsh[k - 1][D + 1][lx] = Gc;
+    }
+    __syncthreads();
+    if (k == 0) {
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) Gu[c] += gsh[kk][c][lx];
+            Gs += gsh[kk][D][lx];
+            Gc += gsh[kk][D + 1][lx];
+        }
+        const double Ge = p.beta0 * (p.a1_b * Gs + p.a2_b * p.beta0 * p.half_xi2 * Gc);
+#pragma unroll
+        for (int c = 0; c < D; ++c) Gu[c] = bx * Gu[c] + p.a5 * p.beta0 * u[c] * Gs;
+        // lam_n,j0 = (1 - omega) g_j + omega h_0 + omega/T (G_u.(e_j - u) + G_eps (|e_j - u|^2/2 - eps))
+        //          = (1 - omega) g_j + K0 + K1.c_j + K2 |c_j|^2
+        const double sc = om * invT;
+        double Gu_u = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) Gu_u += Gu[c] * u[c];
+        const double K0 = om * h + sc * (Ge * (0.5 * uu - eps) - Gu_u);
+        double K1[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < D; ++c) K1[c] = sc * p.xi * (Gu[c] - Ge * u[c]);
+        const double K2 = sc * Ge * p.half_xi2;
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < Q; ++j) {
+                double t = K0 + (csq<Q>(j) == 1 ? K2 : (csq<Q>(j) == 2 ? 2.0 * K2 : 0.0));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if (Lat<Q>::c(j, c) > 0) t += K1[c];
+                    if (Lat<Q>::c(j, c) < 0) t -= K1[c];
+                }
+                put<NTS>(static_cast<T>(omm * static_cast<double>(gr[j]) + t), ln + fidx(Q, nx, row, 0, j, x));
+            }
+        }
+    }
+    if (k == 0 && lx == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4 * kWaves; ++j) t += dsum[j];
+        partials[blockIdx.x] = accumulate ? partials[blockIdx.x] + t : t;
+    }
+}
+
 static dim3 adj_block(int nx) {
     int bx = nx >= 256 ? 256 : (nx >= 128 ? 128 : 64);
     return dim3(bx, 256 / bx, 1);
 }
 
-int adjoint_blocks(int nx, int ny, int nz) {
-    dim3 blk = adj_block(nx);
-    return ((nx + blk.x - 1) / blk.x) * ((ny + blk.y - 1) / blk.y) * nz;
+// Automatic launch shape of the adjoint, from sweeps of the kernel alone on
+// MI355X (one adjoint step, D3Q19 128^3 and D2Q9 512^2): the channel form
+// without a magnetic field (cell form: D3Q19 F64 710, F32 346 us; D2Q9 F64
+// 35.7, F32 20.7 us), 64-cell blocks, the step kernels' store rule;
+//   D3Q19: 8-row interleave, FP64 with at most 2 workgroups per CU (642 us,
+//          0.745 of the HBM peak; uncapped 665 us), FP32 uncapped (316 us);
+//   D2Q9: one row range per XCD, uncapped (F64 33.8, F32 20.1 us).
+AdjointCfg adjoint_launch(int nx, int ny, int nz, int Q, int mode, int field_mode, AdjointCfg want) {
+    AdjointCfg c = want;
+    if (field_mode != kFieldNone) c.form = kAdjCell;
+    if (c.form == kAdjAuto) c.form = kAdjChannel;
+    const double cells = static_cast<double>(nx) * ny * nz;
+    if (c.lc.stores < 0) {
+        const double field_bytes = 4.0 * Q * cells * (mode == kF64 ? 8 : 4);
+        c.lc.stores = field_bytes <= 192.0 * 1048576.0 ? 1 : 0;
+    }
+    if (c.lc.bx == 0) c.lc.bx = 64;
+    if (c.lc.order < 0) c.lc.order = (Q == 9) ? kOrderXcdRange : kOrderInterleave8;
+    if (c.lc.cap < 0) c.lc.cap = (Q == 19 && mode == kF64) ? 2 : 0;
+    return c;
+}
+
+int adjoint_blocks(const KParams& p, int mode, AdjointCfg want) {
+    const AdjointCfg c = adjoint_launch(p.nx, p.ny, p.nz, p.Q, mode, p.field_mode, want);
+    if (c.form == kAdjChannel) return ((p.nx + c.lc.bx - 1) / c.lc.bx) * p.ny * p.nz;
+    const dim3 blk = adj_block(p.nx);
+    return ((p.nx + blk.x - 1) / blk.x) * ((p.ny + blk.y - 1) / blk.y) * p.nz;
+}
+
+template <int Q, int MODE, bool WPULL, int BX>
+static hipError_t adj_channel(const void* Wn, const void* l1, void* l0, const KParams& p, double* partials,
+                              bool accumulate, const LaunchCfg& c, hipStream_t s) {
+    using T = typename Store<MODE>::T;
+    const auto fn = c.stores == 1 ? k_adjoint_channel<Q, MODE, WPULL, BX, false>
+                                  : k_adjoint_channel<Q, MODE, WPULL, BX, true>;
+    const dim3 grd(static_cast<unsigned>((p.nx + BX - 1) / BX) * p.ny * p.nz);
+    const size_t dyn = lds_for_cap(reinterpret_cast<const void*>(fn), BX * 4, c.cap);
+    hipLaunchKernelGGL(fn, grd, dim3(BX, 4), dyn, s, static_cast<const T*>(Wn), static_cast<const T*>(l1),
+                       static_cast<T*>(l0), p, partials, accumulate ? 1 : 0, c.order);
+    return hipGetLastError();
 }
 
 template <int Q, int MODE, int FIELD>
-static hipError_t adj_f(bool wpull, const void* Wn, const void* l1, void* l0, const KParams& p, double* partials,
-                        bool accumulate, hipStream_t s) {
+static hipError_t adj_cell(bool wpull, const void* Wn, const void* l1, void* l0, const KParams& p, double* partials,
+                           bool accumulate, hipStream_t s) {
     using T = typename Store<MODE>::T;
     dim3 blk = adj_block(p.nx);
     dim3 grd((p.nx + blk.x - 1) / blk.x, (p.ny + blk.y - 1) / blk.y, p.nz);
@@ -470,18 +773,27 @@ static hipError_t adj_f(bool wpull, const void* Wn, const void* l1, void* l0, co
 
 template <int Q, int MODE>
 static hipError_t adj_q(bool wpull, const void* Wn, const void* l1, void* l0, const KParams& p, double* partials,
-                        bool accumulate, hipStream_t s) {
-    if (p.field_mode == kFieldUniform) return adj_f<Q, MODE, kFieldUniform>(wpull, Wn, l1, l0, p, partials, accumulate, s);
-    if (p.field_mode == kFieldMap) return adj_f<Q, MODE, kFieldMap>(wpull, Wn, l1, l0, p, partials, accumulate, s);
-    return adj_f<Q, MODE, kFieldNone>(wpull, Wn, l1, l0, p, partials, accumulate, s);
+                        bool accumulate, AdjointCfg want, hipStream_t s) {
+    const AdjointCfg c = adjoint_launch(p.nx, p.ny, p.nz, Q, MODE, p.field_mode, want);
+    if (c.form == kAdjChannel) {
+        if (c.lc.bx == 128) {
+            return wpull ? adj_channel<Q, MODE, true, 128>(Wn, l1, l0, p, partials, accumulate, c.lc, s)
+                         : adj_channel<Q, MODE, false, 128>(Wn, l1, l0, p, partials, accumulate, c.lc, s);
+        }
+        return wpull ? adj_channel<Q, MODE, true, 64>(Wn, l1, l0, p, partials, accumulate, c.lc, s)
+                     : adj_channel<Q, MODE, false, 64>(Wn, l1, l0, p, partials, accumulate, c.lc, s);
+    }
+    if (p.field_mode == kFieldUniform) return adj_cell<Q, MODE, kFieldUniform>(wpull, Wn, l1, l0, p, partials, accumulate, s);
+    if (p.field_mode == kFieldMap) return adj_cell<Q, MODE, kFieldMap>(wpull, Wn, l1, l0, p, partials, accumulate, s);
+    return adj_cell<Q, MODE, kFieldNone>(wpull, Wn, l1, l0, p, partials, accumulate, s);
 }
 
 hipError_t launch_adjoint(int Q, int mode, bool wpull, const void* Wn, const void* lam_next, void* lam_n,
-                          const KParams& p, double* partials, bool accumulate, hipStream_t s) {
-    if (Q == 9) return mode == kF64 ? adj_q<9, kF64>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, s)
-                                    : adj_q<9, kF32>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, s);
-    return mode == kF64 ? adj_q<19, kF64>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, s)
-                        : adj_q<19, kF32>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, s);
+                          const KParams& p, double* partials, bool accumulate, AdjointCfg want, hipStream_t s) {
+    if (Q == 9) return mode == kF64 ? adj_q<9, kF64>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, want, s)
+                                    : adj_q<9, kF32>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, want, s);
+    return mode == kF64 ? adj_q<19, kF64>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, want, s)
+                        : adj_q<19, kF32>(wpull, Wn, lam_next, lam_n, p, partials, accumulate, want, s);
 }
 
 }  // namespace mlbm

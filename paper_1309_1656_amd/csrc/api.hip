@@ -30,6 +30,7 @@ struct mlbm_ctx {
     double f16_scale = 0.0;
     double f16_ref[4][19] = {};
     LaunchCfg launch;               // step launch shape (automatic by default)
+    AdjointCfg adj;                 // adjoint launch shape (automatic by default)
     int device = -1;
     double* d_partials = nullptr;   // reduction partials
     size_t partials_cap = 0;        // in doubles
@@ -124,6 +125,11 @@ int ensure_scratch(mlbm_ctx* h, size_t need) {
 }
 
 int red_scratch(mlbm_ctx* h) { return ensure_scratch(h, static_cast<size_t>(kRedBlocks) * kRedSlots); }
+
+// Partials of the adjoint (nb, one per wave or block) and the tail of their two-stage sum.
+size_t adjoint_scratch(int nb) {
+    return std::max<size_t>(static_cast<size_t>(nb) + kSumChunks, static_cast<size_t>(kRedBlocks) * kRedSlots);
+}
 
 // Host copy of the polynomial factor P_i (Eq. WeqAlgo) for the F16DEV reference.
 double host_P(const mlbm_ctx* h, int i, const double u[3], double eps) {
@@ -265,6 +271,13 @@ int mlbm_get_info(mlbm_handle h, mlbm_info* info) {
     info->launch_order = lc.order;
     info->launch_blocks_per_cu = lc.cap;
     info->launch_temporal_stores = lc.stores;
+    const AdjointCfg ac = adjoint_launch(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz),
+                                         h->Q, h->storage, h->kp.field_mode, h->adj);
+    info->adjoint_form = ac.form;
+    info->adjoint_block_x = ac.form == kAdjChannel ? ac.lc.bx : 0;
+    info->adjoint_order = ac.form == kAdjChannel ? ac.lc.order : -1;
+    info->adjoint_blocks_per_cu = ac.form == kAdjChannel ? ac.lc.cap : 0;
+    info->adjoint_temporal_stores = ac.form == kAdjChannel ? ac.lc.stores : 0;
     info->f16_scale = h->f16_scale;
     for (int k = 0; k < 4; ++k)
         for (int i = 0; i < h->Q; ++i) info->f16_ref[k][i] = h->f16_ref[k][i];
@@ -360,6 +373,21 @@ int mlbm_set_launch(mlbm_handle h, int block_x, int order, int blocks_per_cu) {
     h->launch.bx = block_x;
     h->launch.order = order;
     h->launch.cap = blocks_per_cu;
+    return ok();
+}
+
+int mlbm_set_adjoint_launch(mlbm_handle h, int form, int block_x, int order, int blocks_per_cu, int stores) {
+    if (int e = check_handle(h)) return e;
+    if (form < MLBM_ADJ_AUTO || form > MLBM_ADJ_CELL) return fail(MLBM_EINVAL, "form must be 0, 1 or 2");
+    if (block_x != 0 && block_x != 64 && block_x != 128) return fail(MLBM_EINVAL, "block_x must be 0, 64 or 128");
+    if (order < -1 || order > 2) return fail(MLBM_EINVAL, "order must be -1, 0, 1 or 2");
+    if (blocks_per_cu < -1 || blocks_per_cu > 32) return fail(MLBM_EINVAL, "blocks_per_cu must be in [-1, 32]");
+    if (stores < -1 || stores > 1) return fail(MLBM_EINVAL, "store policy must be -1, 0 or 1");
+    h->adj.form = form;
+    h->adj.lc.bx = block_x;
+    h->adj.lc.order = order;
+    h->adj.lc.cap = blocks_per_cu;
+    h->adj.lc.stores = stores;
     return ok();
 }
 
@@ -589,12 +617,11 @@ int mlbm_adjoint_step(mlbm_handle h, const void* W_n, const void* lam_next, void
     if (h->eq_mode != MLBM_EQ_DIRECT || h->positivity)
         return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode without the positivity limit");
     if (lam_n == W_n || lam_n == lam_next) return fail(MLBM_EINVAL, "lam_n must not alias the inputs");
-    const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));
-    if (int e = ensure_scratch(h, std::max<size_t>(static_cast<size_t>(nb), static_cast<size_t>(kRedBlocks) * kRedSlots)))
-        return e;
+    const int nb = adjoint_blocks(h->kp, h->storage, h->adj);
+    if (int e = ensure_scratch(h, adjoint_scratch(nb))) return e;
     hipStream_t s = as_stream(stream);
-    HIP_TRY(launch_adjoint(h->Q, h->storage, false, W_n, lam_next, lam_n, h->kp, h->d_partials, false, s));
-    if (dL_domega) HIP_TRY(launch_finalize(h->d_partials, nb, 1, 0u, nullptr, dL_domega, 1.0, s));
+    HIP_TRY(launch_adjoint(h->Q, h->storage, false, W_n, lam_next, lam_n, h->kp, h->d_partials, false, h->adj, s));
+    if (dL_domega) HIP_TRY(launch_sum_into(h->d_partials, nb, h->d_partials + nb, dL_domega, 1.0, s));
     return ok();
 }
 
@@ -608,15 +635,15 @@ static int adjoint_checks(mlbm_handle h, const void* W, const void* states, int 
         return fail(MLBM_EINVAL, "the adjoint needs the direct equilibrium mode without the positivity limit");
     if (lam == lam_tmp || lam == W || lam_tmp == W) return fail(MLBM_EINVAL, "lam, lam_tmp and W must be distinct");
     if (nsteps == 0) return MLBM_OK;
-    const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));
-    return ensure_scratch(h, std::max<size_t>(static_cast<size_t>(nb), static_cast<size_t>(kRedBlocks) * kRedSlots));
+    const int nb = adjoint_blocks(h->kp, h->storage, h->adj);
+    return ensure_scratch(h, adjoint_scratch(nb));
 }
 
 // Reverse sweep over nsteps adjoint steps: step j reads W_j, gathered from
 // states[j - 1] (post-collision) for j >= 1 and W itself for j = 0.
 static int adjoint_reverse(mlbm_handle h, const void* W, const char* st, int nsteps, void* lam, void* lam_tmp,
                            double* dL_domega, hipStream_t s) {
-    const int nb = adjoint_blocks(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz));
+    const int nb = adjoint_blocks(h->kp, h->storage, h->adj);
     size_t fb = 0;
     mlbm_field_bytes(h, &fb);
     void* in = lam;
@@ -625,12 +652,12 @@ static int adjoint_reverse(mlbm_handle h, const void* W, const char* st, int nst
         const bool pulled = j > 0;
         const void* wsrc = pulled ? static_cast<const void*>(st + (j - 1) * fb) : W;
         // block partials of dL/domega accumulate over the sweep: one final sum
-        HIP_TRY(launch_adjoint(h->Q, h->storage, pulled, wsrc, in, out, h->kp, h->d_partials, j < nsteps - 1, s));
+        HIP_TRY(launch_adjoint(h->Q, h->storage, pulled, wsrc, in, out, h->kp, h->d_partials, j < nsteps - 1, h->adj, s));
         void* t = in;
         in = out;
         out = t;
     }
-    if (dL_domega) HIP_TRY(launch_finalize(h->d_partials, nb, 1, 0u, nullptr, dL_domega, 1.0, s));
+    if (dL_domega) HIP_TRY(launch_sum_into(h->d_partials, nb, h->d_partials + nb, dL_domega, 1.0, s));
     if (in != lam) HIP_TRY(hipMemcpyAsync(lam, in, fb, hipMemcpyDeviceToDevice, s));
     return ok();
 }

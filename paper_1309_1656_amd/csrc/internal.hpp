@@ -20,6 +20,10 @@ struct LaunchCfg {
 };
 LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want);
 
+// Dynamic LDS that holds a kernel (launched with `threads` threads per
+// workgroup) to at most `cap` resident workgroups per CU; 0 for cap <= 0.
+size_t lds_for_cap(const void* fn, int threads, int cap);
+
 // Gauss-Legendre rule on [-1, 1] used by the device Fermi-Dirac integrals.
 constexpr int kGL = 20;
 struct FdParams {
@@ -47,11 +51,23 @@ hipError_t launch_relaxation(int Q, int mode, const void* W, const double* g, co
 hipError_t launch_spin_loss(int Q, int mode, const void* W, const double* r_target, void* lam,
                             const KParams& p, double* partials, hipStream_t s);
 
+// Launch shape of the adjoint kernels: the form (kAdjAuto, kAdjChannel: one
+// wave per Pauli channel on row-blocked cells like the step passes,
+// kAdjCell: one thread per cell with all four channels) and, for the channel
+// form, the step kernels' shape parameters (block width, order, cap, stores).
+// The magnetic-field adjoint exists in the cell form only.
+enum { kAdjAuto = 0, kAdjChannel = 1, kAdjCell = 2 };
+struct AdjointCfg {
+    int form = kAdjAuto;
+    LaunchCfg lc;
+};
+AdjointCfg adjoint_launch(int nx, int ny, int nz, int Q, int mode, int field_mode, AdjointCfg want);
+
 // Adjoint of one step: one partial of dL/domega per block
-// (adjoint_blocks(nx, ny, nz) values, stride 1).  With wpull, Wn is the
+// (adjoint_blocks(...) values, stride 1).  With wpull, Wn is the
 // previous post-collision state and W_n is gathered from it by a pull.
 hipError_t launch_adjoint(int Q, int mode, bool wpull, const void* Wn, const void* lam_next, void* lam_n,
-                          const KParams& p, double* partials, bool accumulate, hipStream_t s);
+                          const KParams& p, double* partials, bool accumulate, AdjointCfg want, hipStream_t s);
 
 // Initial Fermi-Dirac state.  phase 0: only reduce global sums (slots 0..3
 // rho_k, 4..6 tr(rho) u, 7 total energy); phase 1: reduce max |a - R| / w_i
@@ -71,8 +87,16 @@ hipError_t launch_init(int Q, int mode, int phase, int src, void* W, const doubl
 hipError_t launch_finalize(const double* partials, int nblocks, int stride, unsigned max_mask, double* out,
                            double* accumulate_into, double scale0, hipStream_t s);
 
-// Number of blocks (= partials) of launch_adjoint for a grid.
-int adjoint_blocks(int nx, int ny, int nz);
+// accumulate_into[0] += scale0 * sum of x[0 .. n), reduced in a fixed order.
+// Up to kSumDirect values in one block; longer sums first reduce at most
+// kSumChunks consecutive chunks in parallel into tail[0 .. kSumChunks).
+constexpr int kSumDirect = 4096;
+constexpr int kSumChunks = 1024;
+hipError_t launch_sum_into(const double* x, size_t n, double* tail, double* accumulate_into, double scale0,
+                           hipStream_t s);
+
+// Number of blocks (= partials) of launch_adjoint for a grid and configuration.
+int adjoint_blocks(const KParams& p, int mode, AdjointCfg want);
 
 // Flat copy of n16 16-byte vectors (16-byte aligned, non-overlapping).
 hipError_t launch_copy16(const void* src, void* dst, size_t n16, hipStream_t s);

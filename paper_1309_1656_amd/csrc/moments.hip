@@ -181,9 +181,18 @@ k_finalize(const double* __restrict__ partials, int nblocks, int stride, unsigne
     for (int s = 0; s < kRedSlots; ++s) {
         const bool is_max = (max_mask >> s) & 1u;
         double v = is_max ? -1.0e300 : 0.0;
-        for (int j = t; j < nblocks && s < stride; j += kRedThreads) {
-            const double o = partials[static_cast<size_t>(j) * stride + s];
-            v = is_max ? fmax(v, o) : v + o;
+        // rows t, t + kRedThreads, ... in order; eight loads in flight at a time
+        for (int j0 = t; j0 < nblocks && s < stride; j0 += 8 * kRedThreads) {
+            double o[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int j = j0 + q * kRedThreads;
+                o[q] = partials[static_cast<size_t>(j < nblocks ? j : nblocks - 1) * stride + s];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (j0 + q * kRedThreads < nblocks) v = is_max ? fmax(v, o[q]) : v + o[q];
+            }
         }
         sh[s][t] = v;
     }
@@ -204,6 +213,37 @@ k_finalize(const double* __restrict__ partials, int nblocks, int stride, unsigne
             out[t] = (t == 0) ? scale0 * sh[0][0] : sh[t][0];
         }
     }
+}
+
+// First stage of a long sum: block b reduces the consecutive chunk
+// [b chunk, (b + 1) chunk) of x (each thread a fixed stride, then a fixed LDS
+// tree) into out[b].  Reproducible for a given n.
+__global__ void __launch_bounds__(kRedThreads)
+k_chunk_sums(const double* __restrict__ x, size_t n, size_t chunk, double* __restrict__ out) {
+    __shared__ double sh[kRedThreads];
+    const int t = threadIdx.x;
+    const size_t lo = static_cast<size_t>(blockIdx.x) * chunk;
+    const size_t hi = lo + chunk < n ? lo + chunk : n;
+    double v = 0.0;
+    for (size_t j0 = lo + t; j0 < hi; j0 += 8 * kRedThreads) {
+        double o[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const size_t j = j0 + q * kRedThreads;
+            o[q] = x[j < hi ? j : hi - 1];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (j0 + q * kRedThreads < hi) v += o[q];
+        }
+    }
+    sh[t] = v;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[blockIdx.x] = sh[0];
 }
 
 template <int Q, int MODE>
@@ -262,6 +302,19 @@ hipError_t launch_spin_loss(int Q, int mode, const void* W, const double* r_targ
                                     : loss_q<9, kF32>(W, r_target, lam, p, partials, s);
     return mode == kF64 ? loss_q<19, kF64>(W, r_target, lam, p, partials, s)
                         : loss_q<19, kF32>(W, r_target, lam, p, partials, s);
+}
+
+hipError_t launch_sum_into(const double* x, size_t n, double* tail, double* accumulate_into, double scale0,
+                           hipStream_t s) {
+    if (n <= static_cast<size_t>(kSumDirect))
+        return launch_finalize(x, static_cast<int>(n), 1, 0u, nullptr, accumulate_into, scale0, s);
+    // chunk: a multiple of the block size, so that at most kSumChunks chunks cover n
+    const size_t per = (n + kSumChunks - 1) / kSumChunks;
+    const size_t chunk = (per + kRedThreads - 1) / kRedThreads * kRedThreads;
+    const size_t nchunk = (n + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_chunk_sums, dim3(static_cast<unsigned>(nchunk)), dim3(kRedThreads), 0, s, x, n, chunk, tail);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    return launch_finalize(tail, static_cast<int>(nchunk), 1, 0u, nullptr, accumulate_into, scale0, s);
 }
 
 hipError_t launch_finalize(const double* partials, int nblocks, int stride, unsigned max_mask, double* out,

@@ -30,6 +30,7 @@
 #include <mutex>
 #include <utility>
 
+#include "block_order.hpp"
 #include "common.hpp"
 #include "fermi_device.hpp"
 #include "internal.hpp"
@@ -40,9 +41,12 @@ namespace mlbm {
 // coefficients) carry fixed rounding errors, so an uncorrected float
 // collision gains or loses a fixed ~1e-8 of the conserved moments every step
 // and the global averages drift.  (With FP16 storage the half-precision
-// quantisation of the deviations dominates instead, so the correction is not
-// applied there.)  The defect of the rounded outputs is summed
-// in double and folded back exactly:
+// rounding of the stored deviations dominates instead: a cell near a steady
+// state rounds the same way step after step, and folding each cell's rounding
+// defect into its rest and axis populations, measured, cut the drift by 1.3x
+// only while slowing the pass by 40%, so the correction is not applied there.)
+// The defect of the float outputs is summed in double and folded back exactly
+// (fold_defect):
 //   every channel k: mass sum_i (S_ik - a_ik) is removed from the rest population;
 //   trace channel: momentum component d is removed through the axis pair
 //   (+d, -d) (opposite halves: mass and energy unchanged), and energy through
@@ -52,18 +56,9 @@ namespace mlbm {
 // rounding per value, which has no preferred sign.  ENERGY = false (isothermal
 // model, where the collision changes the energy on purpose) corrects mass and
 // momentum only.
-template <int Q, typename C, bool ENERGY = true>
-__device__ __forceinline__ void conserve(C (&S)[Q], const C (&a)[Q], int k) {
+template <int Q, typename C>
+__device__ __forceinline__ void fold_defect(C (&S)[Q], int k, double dm, const double (&dj)[3], double dE) {
     constexpr int D = Lat<Q>::D;
-    double dm = 0.0, dj[3] = {0.0, 0.0, 0.0}, dE = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double dd = static_cast<double>(S[i]) - static_cast<double>(a[i]);
-        dm += dd;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) dj[c] += Lat<Q>::c(i, c) * dd;
-        if constexpr (ENERGY) dE += csq<Q>(i) * dd;
-    }
     if (k != 0) {
         S[0] = static_cast<C>(static_cast<double>(S[0]) - dm);
         return;
@@ -79,43 +74,18 @@ __device__ __forceinline__ void conserve(C (&S)[Q], const C (&a)[Q], int k) {
     }
 }
 
-// Block order.  The grid is one-dimensional and the hardware hands block b to
-// XCD b mod 8 (round robin); each XCD has its own L2.  Blocks that cover
-// neighbouring x-chunks of one row read the same boundary cache lines (the
-// x-shifted pulls).  Three bijections of [0, gridDim.x) onto (chunk, row):
-//   kOrderNatural     chunk fastest, rows in order;
-//   kOrderXcdRange    every XCD runs one contiguous range of logical blocks,
-//                     so the chunks of a row share an L2;
-//   kOrderInterleave8 8 consecutive rows go to the 8 XCDs and the chunks of a
-//                     row follow 8 blocks apart on the same XCD; rows are
-//                     still swept in order across the chip.
-// Which is fastest depends on the grid (measured on MI355X; see step_launch).
-__device__ __forceinline__ void block_order(int order, int nx, int ny, int bx, int& chunk, int& y, int& z) {
-    constexpr unsigned kXcd = 8;
-    const unsigned b = blockIdx.x, G = gridDim.x;
-    const unsigned nchunk = (static_cast<unsigned>(nx) + bx - 1) / bx;
-    unsigned row, ch;
-    if (order == kOrderInterleave8) {
-        const unsigned grp = kXcd * nchunk, g = b / grp, t = b % grp;
-        if (g < G / grp) {
-            ch = t / kXcd;
-            row = g * kXcd + t % kXcd;
-        } else {          // last, partial group of rows: natural order
-            ch = t % nchunk;
-            row = g * kXcd + t / nchunk;
-        }
-    } else {
-        unsigned L = b;
-        if (order == kOrderXcdRange) {
-            const unsigned q = G / kXcd, r = G % kXcd, j = b % kXcd;
-            L = j * q + (j < r ? j : r) + b / kXcd;
-        }
-        row = L / nchunk;
-        ch = L - row * nchunk;
+template <int Q, typename C, bool ENERGY = true>
+__device__ __forceinline__ void conserve(C (&S)[Q], const C (&a)[Q], int k) {
+    double dm = 0.0, dj[3] = {0.0, 0.0, 0.0}, dE = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double dd = static_cast<double>(S[i]) - static_cast<double>(a[i]);
+        dm += dd;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dj[c] += Lat<Q>::c(i, c) * dd;
+        if constexpr (ENERGY) dE += csq<Q>(i) * dd;
     }
-    chunk = static_cast<int>(ch);
-    y = static_cast<int>(row % static_cast<unsigned>(ny));
-    z = static_cast<int>(row / static_cast<unsigned>(ny));
+    fold_defect<Q, C>(S, k, dm, dj, dE);
 }
 
 // Positivity-limited relaxation (Sec. 3.3, paragraph after the algorithm):
@@ -157,10 +127,25 @@ __device__ __forceinline__ void store_field(T v, T* ptr) {
     else *ptr = v;
 }
 
+// Field pointers of k_step.  Every pass that streams reads and writes distinct
+// fields, so its pointers are restrict-qualified; the collide-only pass may run
+// in place (src == dst: mlbm_step with an even step count, mlbm_collide), so
+// its pointers are plain.  In place, every element is read and then written by
+// the same thread.
+template <bool DISTINCT, typename T> struct FieldPtr {
+    using in = const T*;
+    using out = T*;
+};
+template <typename T> struct FieldPtr<true, T> {
+    using in = const T* __restrict__;
+    using out = T* __restrict__;
+};
+
 template <int Q, int MODE, bool PULL, bool COLL, int BX, int FIELD, int VAR, bool NTS = true>
 __global__ void __launch_bounds__(BX * 4)
-k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T* __restrict__ dst,
-       const KParams p, const int order, const FdParams fp) {
+k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
+       typename FieldPtr<PULL, typename Store<MODE>::T>::out dst, const KParams p, const int order,
+       const FdParams fp) {
     using T = typename Store<MODE>::T;
     using C = typename Store<MODE>::C;
     constexpr int D = Lat<Q>::D;
@@ -371,11 +356,15 @@ k_step(const typename Store<MODE>::T* __restrict__ src, typename Store<MODE>::T*
 //     from 128^3 on (6.03 against 5.93 TB/s); larger D3Q19 grids 128-cell
 //     blocks, per-XCD ranges; D2Q9 128-cell blocks, 8-row interleave;
 //   FP16: as FP32 without a cap (it gains nothing there).
-// Field writes are temporal when one field holds at most 192 MiB, so that the
-// two fields of a pass can stay in the 256 MB last-level cache between passes
-// (D2Q9 512^2 FP32 13.7 against 15.8 us per pass, D3Q19 64^3 FP32 26.0
-// against 29.9 us); larger fields use streaming stores (D3Q19 128^3 FP64 424
-// against 445 us, D2Q9 1024^2 FP64 98 against 102 us).
+// Field writes are temporal when one field holds at most 192 MiB and
+// streaming above.  The threshold is an empirical cut-off between measured
+// per-pass times, not a capacity bound: the two fields of a pass can together
+// exceed the 256 MB last-level cache below it (D2Q9 1024^2 FP32: 151 MB per
+// field), and part of what the next pass reads is still found there.
+// Temporal: D2Q9 512^2 FP32 13.7 against 15.8 us per pass, D3Q19 64^3 FP32
+// 26.0 against 29.9 us, D2Q9 1024^2 FP32 48.7 against 50.6 us.  Streaming:
+// D3Q19 128^3 FP64 (1.27 GB per field) 424 against 445 us, D2Q9 1024^2 FP64
+// (302 MB) 98 against 102 us.
 // The cap and the temporal stores are not applied to the magnetic-field
 // kernels (more LDS) and to the isothermal and positivity kernels (more
 // arithmetic per cell).
@@ -405,7 +394,7 @@ LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want) {
 // bandwidth the pass reaches; the LDS is reserved, never touched.  The size is
 // the smallest one at which the runtime's occupancy calculator reports at
 // most `cap` workgroups, found once per kernel and cap and cached.
-static size_t lds_for_cap(const void* fn, int threads, int cap) {
+size_t lds_for_cap(const void* fn, int threads, int cap) {
     if (cap <= 0) return 0;
     static std::mutex mu;
     static std::map<std::pair<const void*, int>, size_t> cache;

@@ -15,6 +15,7 @@ MLBM_D2Q9, MLBM_D3Q19 = 9, 19
 MLBM_STORE_F64, MLBM_STORE_F32, MLBM_STORE_F16DEV = 0, 1, 2
 MLBM_EQ_DIRECT, MLBM_EQ_EIGEN, MLBM_EQ_ISOTHERMAL = 0, 1, 2
 MLBM_ORDER_AUTO, MLBM_ORDER_NATURAL, MLBM_ORDER_XCD_RANGE, MLBM_ORDER_INTERLEAVE8 = -1, 0, 1, 2
+MLBM_ADJ_AUTO, MLBM_ADJ_CHANNEL, MLBM_ADJ_CELL = 0, 1, 2
 MLBM_OK, MLBM_EINVAL, MLBM_EDOMAIN, MLBM_EHIP, MLBM_ENOMEM, MLBM_ENONFINITE, MLBM_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmlbm.so")
@@ -24,7 +25,7 @@ EXPORTS = (
     "mlbm_init_equilibrium", "mlbm_step", "mlbm_collide", "mlbm_stream", "mlbm_moments", "mlbm_spin_loss",
     "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_step_states", "mlbm_adjoint_sweep", "mlbm_set_f16_reference", "mlbm_set_launch",
     "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_init_chemical", "mlbm_relaxation", "mlbm_set_positivity",
-    "mlbm_device_copy", "mlbm_set_store_policy", "mlbm_last_error",
+    "mlbm_device_copy", "mlbm_set_store_policy", "mlbm_set_adjoint_launch", "mlbm_last_error",
 )
 
 
@@ -46,6 +47,8 @@ class Info(ctypes.Structure):
         ("launch_block_x", ctypes.c_int), ("launch_order", ctypes.c_int),
         ("f16_scale", ctypes.c_double), ("f16_ref", (ctypes.c_double * 19) * 4),
         ("launch_blocks_per_cu", ctypes.c_int), ("launch_temporal_stores", ctypes.c_int),
+        ("adjoint_form", ctypes.c_int), ("adjoint_block_x", ctypes.c_int), ("adjoint_order", ctypes.c_int),
+        ("adjoint_blocks_per_cu", ctypes.c_int), ("adjoint_temporal_stores", ctypes.c_int),
     ]
 
 
@@ -87,6 +90,8 @@ def load_library(path=LIB_PATH):
         "mlbm_set_positivity": ([vp, ctypes.c_int], ctypes.c_int),
         "mlbm_device_copy": ([vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "mlbm_set_store_policy": ([vp, ctypes.c_int], ctypes.c_int),
+        "mlbm_set_adjoint_launch": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+                                    ctypes.c_int),
         "mlbm_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -375,6 +380,12 @@ def mlbm_set_launch(h, block_x=0, order=MLBM_ORDER_AUTO, blocks_per_cu=-1):
 def mlbm_set_store_policy(h, policy=-1):
     """-1 automatic, 0 streaming (non-temporal) field writes, 1 temporal."""
     _check(load_library().mlbm_set_store_policy(h.ptr, int(policy)))
+    mlbm_get_info(h)
+
+
+def mlbm_set_adjoint_launch(h, form=MLBM_ADJ_AUTO, block_x=0, order=MLBM_ORDER_AUTO, blocks_per_cu=-1, stores=-1):
+    _check(load_library().mlbm_set_adjoint_launch(h.ptr, int(form), int(block_x), int(order), int(blocks_per_cu),
+                                                  int(stores)))
     mlbm_get_info(h)
 
 
