@@ -248,3 +248,32 @@ def test_store_policy():
         with pytest.raises(mlbm.MlbmError) as e:
             mlbm.mlbm_set_store_policy(h, bad)
         assert e.value.code == mlbm.MLBM_EINVAL
+
+
+def test_adjoint_launch_shape():
+    """Automatic adjoint shape: the channel form (64-cell blocks; D3Q19 8-row interleave, FP64 capped
+    at 2 workgroups per CU; D2Q9 per-XCD row ranges) without a field, the cell form with one; the
+    setter validates its arguments and mlbm_get_info reports the shape in effect."""
+    h = mlbm.mlbm_create(19, (128, 128, 128), 0.8, 1.0, mlbm.MLBM_STORE_F64)
+    i = h.info
+    assert (i["adjoint_form"], i["adjoint_block_x"], i["adjoint_order"], i["adjoint_blocks_per_cu"]) == (
+        mlbm.MLBM_ADJ_CHANNEL, 64, mlbm.MLBM_ORDER_INTERLEAVE8, 2)
+    assert i["adjoint_temporal_stores"] == 0
+    h32 = mlbm.mlbm_create(9, (512, 512, 1), 0.8, 1.0, mlbm.MLBM_STORE_F32)
+    i = h32.info
+    assert (i["adjoint_form"], i["adjoint_block_x"], i["adjoint_order"], i["adjoint_blocks_per_cu"]) == (
+        mlbm.MLBM_ADJ_CHANNEL, 64, mlbm.MLBM_ORDER_XCD_RANGE, 0)
+    assert i["adjoint_temporal_stores"] == 1
+    mlbm.mlbm_set_adjoint_launch(h, mlbm.MLBM_ADJ_CHANNEL, 128, mlbm.MLBM_ORDER_NATURAL, 3, 1)
+    i = h.info
+    assert (i["adjoint_block_x"], i["adjoint_order"], i["adjoint_blocks_per_cu"], i["adjoint_temporal_stores"]) == (
+        128, mlbm.MLBM_ORDER_NATURAL, 3, 1)
+    mlbm.mlbm_set_adjoint_launch(h, mlbm.MLBM_ADJ_CELL)
+    assert h.info["adjoint_form"] == mlbm.MLBM_ADJ_CELL and h.info["adjoint_block_x"] == 0
+    mlbm.mlbm_set_adjoint_launch(h)
+    mlbm.mlbm_set_magnetic_field(h, [0.0, 0.1, 0.0])
+    assert h.info["adjoint_form"] == mlbm.MLBM_ADJ_CELL       # the field runs in the cell form only
+    for bad in ((3, 0, -1, -1, -1), (0, 96, -1, -1, -1), (0, 0, 3, -1, -1), (0, 0, -1, 33, -1), (0, 0, -1, -1, 2)):
+        with pytest.raises(mlbm.MlbmError) as e:
+            mlbm.mlbm_set_adjoint_launch(h, *bad)
+        assert e.value.code == mlbm.MLBM_EINVAL
