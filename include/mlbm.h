@@ -307,6 +307,28 @@ int mlbm_moments(mlbm_handle h, const void* W, double* rho4, double* u,
                  double* eps, double* global8, int64_t* n_neg_eig, void* stream);
 
 /*
+ * mlbm_moments_noalloc -- mlbm_moments for callers that cannot allocate
+ * device memory or synchronise (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same kernels and fixed-order
+ * reduction, with no host output, no allocation and no synchronisation.
+ *   rho4, u, eps as for mlbm_moments (device, each may be NULL);
+ *   sums [10] double (device) or NULL: the SUMS over cells (not averages) of
+ *        the 4 Pauli coefficients of rho, of tr(rho) u (3 entries, third 0 in
+ *        2D) and of tr(rho)(eps + |u|^2/2); then the number of populations
+ *        with a negative eigenvalue and the number of non-finite values, as
+ *        doubles.  Divided by N, entries 0..7 are mlbm_moments' global8.
+ * The reduction buffer is a fixed-size array in device memory (1024 x 10
+ * doubles, 80 KiB, whatever the lattice size) that each GPU holds from the
+ * first call until the process ends; the first call on a device also looks
+ * up its address.  Every call on one GPU shares that buffer, so calls that
+ * overlap in time on one GPU (other streams, other handles, other host
+ * threads) race: order them.  Non-finite values are counted, not reported as
+ * an error.  Errors: MLBM_EINVAL (null handle or W), MLBM_EHIP.
+ */
+int mlbm_moments_noalloc(mlbm_handle h, const void* W, double* rho4, double* u,
+                         double* eps, double* sums, void* stream);
+
+/*
  * mlbm_relaxation -- how far field W is from the uniform state it relaxes to
  * (Sec. 4, convergence to equilibrium), and the split of the global energy
  * (Sec. 4, interference: the total is conserved, the internal part is not).

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "constants.hpp"
@@ -155,6 +156,31 @@ int check_init_flags(const double r[kRedSlots]) {
     if (r[8] > 0) return fail(MLBM_EDOMAIN, "%.0f cells outside the Fermi-Dirac domain "
                                             "(need tr rho > 0, |r| < tr rho, T > 0, finite values)", r[8]);
     if (r[9] > 0) return fail(MLBM_ENOCONV, "Fermi-Dirac inversion failed in %.0f cells", r[9]);
+    return MLBM_OK;
+}
+
+// Reduction buffer of mlbm_moments_noalloc: a file-scope device array, so that
+// the call allocates nothing.  Every GPU holds its own copy until the process
+// ends; host code uses only the address hipGetSymbolAddress returns for the
+// current device (the array's name is not a device address in host code).
+constexpr size_t kNoAllocDoubles = static_cast<size_t>(kRedBlocks) * kRedSlots;
+__device__ __align__(256) double noalloc_scratch[kNoAllocDoubles];
+constexpr int kMaxDevices = 64;
+
+// Device address of noalloc_scratch on the current device, looked up once per device.
+int noalloc_scratch_ptr(double** out) {
+    static std::mutex mu;
+    static double* ptrs[kMaxDevices] = {};
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MLBM_EINVAL, "device %d outside the supported 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptrs[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)));
+        ptrs[dev] = static_cast<double*>(p);
+    }
+    *out = ptrs[dev];
     return MLBM_OK;
 }
 
@@ -565,6 +591,20 @@ int mlbm_moments(mlbm_handle h, const void* W, double* rho4, double* u, double* 
     }
     if (n_neg_eig) *n_neg_eig = static_cast<int64_t>(r[8]);
     if (r[9] > 0) return fail(MLBM_ENONFINITE, "%.0f non-finite values in the field", r[9]);
+    return ok();
+}
+
+int mlbm_moments_noalloc(mlbm_handle h, const void* W, double* rho4, double* u, double* eps, double* sums,
+                         void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!W) return fail(MLBM_EINVAL, "null field");
+    // the reduction uses a fixed grid of kRedBlocks blocks, whatever the lattice size
+    static_assert(static_cast<size_t>(kRedBlocks) * kRedSlots <= kNoAllocDoubles, "reduction buffer too small");
+    double* scratch = nullptr;
+    if (int e = noalloc_scratch_ptr(&scratch)) return e;
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(launch_moments(h->Q, h->storage, W, rho4, u, eps, h->kp, scratch, s));
+    if (sums) HIP_TRY(launch_finalize(scratch, kRedBlocks, kRedSlots, 0u, sums, nullptr, 1.0, s));
     return ok();
 }
 

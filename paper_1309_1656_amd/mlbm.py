@@ -25,7 +25,8 @@ EXPORTS = (
     "mlbm_init_equilibrium", "mlbm_step", "mlbm_collide", "mlbm_stream", "mlbm_moments", "mlbm_spin_loss",
     "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_step_states", "mlbm_adjoint_sweep", "mlbm_set_f16_reference", "mlbm_set_launch",
     "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_init_chemical", "mlbm_relaxation", "mlbm_set_positivity",
-    "mlbm_device_copy", "mlbm_set_store_policy", "mlbm_set_adjoint_launch", "mlbm_last_error",
+    "mlbm_device_copy", "mlbm_set_store_policy", "mlbm_set_adjoint_launch", "mlbm_moments_noalloc",
+    "mlbm_last_error",
 )
 
 
@@ -76,6 +77,7 @@ def load_library(path=LIB_PATH):
         "mlbm_collide": ([vp, vp, vp, vp], ctypes.c_int),
         "mlbm_stream": ([vp, vp, vp, vp], ctypes.c_int),
         "mlbm_moments": ([vp, vp, vp, vp, vp, dp, i64p, vp], ctypes.c_int),
+        "mlbm_moments_noalloc": ([vp, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_spin_loss": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_adjoint_step": ([vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_adjoint_segment": ([vp, vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
@@ -319,6 +321,14 @@ def mlbm_moments(h, W, rho4=None, u=None, eps=None, host=True, stream=None):
     if host:
         return np.array(g[:]), int(nneg.value)
     return None
+
+
+def mlbm_moments_noalloc(h, W, rho4=None, u=None, eps=None, sums=None, stream=None):
+    """mlbm_moments without allocation or synchronisation; sums: float64 device tensor of 10 values or None."""
+    import torch
+    _check(load_library().mlbm_moments_noalloc(
+        h.ptr, _field_ptr(h, W, "W"), _f64_ptr(h, rho4, 4, "rho4"), _f64_ptr(h, u, h.info["d"], "u"),
+        _f64_ptr(h, eps, 1, "eps"), _dev_ptr(sums, torch.float64, 10, "sums"), _stream_ptr(stream)))
 
 
 RELAXATION_KEYS = ("max_drho", "max_du", "max_detot", "internal_energy", "kinetic_energy",

@@ -105,6 +105,8 @@ int main(void) {
     EXPECT(mlbm_set_adjoint_launch(h, MLBM_ADJ_AUTO, 0, MLBM_ORDER_AUTO, 33, -1), MLBM_EINVAL);
     EXPECT(mlbm_set_adjoint_launch(h, MLBM_ADJ_AUTO, 0, MLBM_ORDER_AUTO, -1, 2), MLBM_EINVAL);
     EXPECT(mlbm_set_adjoint_launch(h, MLBM_ADJ_AUTO, 0, MLBM_ORDER_AUTO, -1, -1), MLBM_OK);
+    EXPECT(mlbm_moments_noalloc(NULL, p1, NULL, NULL, NULL, NULL, NULL), MLBM_EINVAL);
+    EXPECT(mlbm_moments_noalloc(h, NULL, NULL, NULL, NULL, NULL, NULL), MLBM_EINVAL);
     EXPECT(mlbm_device_copy(NULL, p2, 64, NULL), MLBM_EINVAL);
     EXPECT(mlbm_device_copy(p1, p2, 24, NULL), MLBM_EINVAL);                /* not a multiple of 16 */
     EXPECT(mlbm_device_copy((void*)0x1008, p2, 64, NULL), MLBM_EINVAL);     /* misaligned */
