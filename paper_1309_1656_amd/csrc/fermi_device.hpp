@@ -109,6 +109,52 @@ __device__ void series_pair(double x, double& sa, double& sb) {
     }
 }
 
+// Three series of the same argument in one pass.
+template <int TWO_A, int TWO_B, int TWO_C>
+__device__ void series_triple(double x, double& sa, double& sb, double& sc) {
+    const double t = exp(x);
+    double pj = t;
+    sa = 0.0;
+    sb = 0.0;
+    sc = 0.0;
+    for (int j = 1; j <= kSeriesTerms; ++j) {
+        const double ta = pj * jpow_inv<TWO_A>(j), tb = pj * jpow_inv<TWO_B>(j), tc = pj * jpow_inv<TWO_C>(j);
+        sa += (j & 1) ? ta : -ta;
+        sb += (j & 1) ? tb : -tb;
+        sc += (j & 1) ? tc : -tc;
+        if (ta <= 1e-18 * sa && tb <= 1e-18 * sb && tc <= 1e-18 * sc) break;
+        pj *= t;
+    }
+}
+
+// Reversion of the series F_{1/2}(x) = sum_j (-1)^(j+1) z^j / j^(3/2), z = e^x:
+// z = sum_{n=1..kRev} g_n c^n solves F_{1/2}(x) = c up to O(c^(kRev+1)).  The
+// g_n follow by composing term by term: with g_1 = 1, g_n is minus the c^n
+// coefficient of f(g(c)) computed with g_n = 0 (computed at compile time).
+constexpr int kRev = 8;
+struct HalfReversion {
+    double g[kRev + 1];
+    constexpr HalfReversion() : g() {
+        double f[kRev + 1] = {};
+        for (int j = 1; j <= kRev; ++j) f[j] = ((j & 1) ? 1.0 : -1.0) / (j * const_sqrt(static_cast<double>(j)));
+        g[1] = 1.0;
+        for (int n = 2; n <= kRev; ++n) {
+            double cur[kRev + 1] = {};          // g(c)^m, truncated at degree kRev
+            for (int q = 1; q <= kRev; ++q) cur[q] = g[q];
+            double acc = 0.0;
+            for (int m = 1; m <= n; ++m) {
+                acc += f[m] * cur[n];
+                double nxt[kRev + 1] = {};
+                for (int a = 1; a <= kRev; ++a)
+                    for (int b = 1; a + b <= kRev; ++b) nxt[a + b] += cur[a] * g[b];
+                for (int q = 0; q <= kRev; ++q) cur[q] = nxt[q];
+            }
+            g[n] = -acc;
+        }
+    }
+};
+__constant__ const HalfReversion kHalfRev{};
+
 // F_{M - 1/2}(x) by the trapezoidal rule described above, x > -1.
 // Arguments above kXMax (or NaN) return NaN: the step count grows like x,
 // and such degenerate states are outside the supported range.
@@ -213,6 +259,31 @@ __device__ __forceinline__ bool invert_half_fast(double c, double& nu) {
     return false;
 }
 
+// Dilute 3D channel (c = F_{1/2}(nu) <= 0.2, so nu <= -1.5): F_{3/2}(nu) with
+// few series passes.  The reversed series starts Newton within ~1e-15 of the
+// root; each Newton step takes one pass that sums F_{3/2}, F_{1/2} and
+// F_{-1/2} together.  Once a step d is below 1e-8 (the next one would be of
+// order d^2), it is taken and F_{3/2} follows it to first order,
+// F_{3/2}(nu - d) = F_{3/2}(nu) - d F_{1/2}(nu) + O(d^2).  False if the
+// iterate leaves the series range or does not settle.
+__device__ __forceinline__ bool iso_half_dilute(double c, double& f32) {
+    double z = kHalfRev.g[kRev];
+    for (int q = kRev - 1; q >= 1; --q) z = z * c + kHalfRev.g[q];
+    double nu = log(z * c);
+    for (int it = 0; it < 8; ++it) {
+        if (!(nu <= -1.0)) return false;
+        double f5, f3, f1;
+        series_triple<5, 3, 1>(nu, f5, f3, f1);
+        const double d = (f3 - c) / f1;
+        nu -= d;
+        if (fabs(d) <= 1e-8 * fmax(1.0, fabs(nu))) {
+            f32 = f5 - d * f3;
+            return isfinite(f32);
+        }
+    }
+    return false;
+}
+
 // One channel of the isothermal energy: F_{d/2}(nu) for the channel density n
 // at inverse temperature beta (NaN if the inversion fails).
 template <int D>
@@ -221,8 +292,11 @@ __device__ __forceinline__ double iso_channel(double beta, double n, const FdPar
     if constexpr (D == 2) {
         return F1(log(expm1(n * s)), fp);
     } else {
+        const double c = n * s * sqrt(s);
+        double f32 = 0.0;
+        if (c <= 0.2 && iso_half_dilute(c, f32)) return f32;
         double nu = 0.0;
-        if (!invert_half_fast(n * s * sqrt(s), nu)) return __builtin_nan("");
+        if (!invert_half_fast(c, nu)) return __builtin_nan("");
         return half<2>(nu);
     }
 }

@@ -196,8 +196,12 @@ k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
         // wave bounds the rate for a quarter of the velocities.
         constexpr bool kIso = (VAR & kVarIso) != 0, kPos = (VAR & kVarPos) != 0;
         static_assert(VAR == 0 || FIELD == kFieldNone, "variants and the field are exclusive");
-        __shared__ C lds[(FIELD != kFieldNone ? 3 : (kPos ? 5 : 1)) * Q * BX];
+        // plain and field kernels: q_i of the trace wave (Q BX values), with a field
+        // reused for the exchange of the three Bloch channels (3 Q BX values);
+        // positivity: all four channels of every population (4 Q BX values)
+        __shared__ C lds[(FIELD != kFieldNone ? 3 : (kPos ? 4 : 1)) * Q * BX];
         __shared__ double rsh[VAR != 0 ? 4 : 1][BX];      // rho_k of the Bloch waves; tr rho
+        __shared__ double jsh[VAR != 0 ? 4 : 1][BX];      // the trace wave's j (3 components) and K
         __shared__ double esh[kIso ? 2 : 1][BX];          // isothermal: F_{d/2}(nu) per eigen-channel
         __shared__ C pmin[kPos ? 4 : 1][BX];              // positivity: each wave's bound on the rate
         C (*qs)[BX] = reinterpret_cast<C (*)[BX]>(lds);
@@ -208,31 +212,9 @@ k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
             a[i] = decode<MODE>(raw[i], k, i, p);
             rk += static_cast<double>(a[i]);
         }
-        if constexpr (VAR != 0) {
-            if (k > 0) rsh[k - 1][lx] = rk;
-            else rsh[3][lx] = rk;
-            if constexpr (kPos) {
-                // channel k at ab[k - 1] (Bloch), the trace at ab[3]
-                C (*ab)[Q][BX] = reinterpret_cast<C (*)[Q][BX]>(lds + Q * BX);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) ab[k > 0 ? k - 1 : 3][i][lx] = a[i];
-            }
-            __syncthreads();
-            if constexpr (kIso) {
-                // isothermal model: the Fermi-Dirac state at beta = beta0 with the
-                // cell's density matrix; its eigen-channels (tr rho +- |rho|)/2 are
-                // inverted by waves 1 (up) and 2 (down) side by side
-                if (k == 1 || k == 2) {
-                    const double rv = sqrt(rsh[0][lx] * rsh[0][lx] + rsh[1][lx] * rsh[1][lx] + rsh[2][lx] * rsh[2][lx]);
-                    const double n = 0.5 * (rsh[3][lx] + (k == 1 ? rv : -rv));
-                    esh[k - 1][lx] = fd::iso_channel<D>(p.beta0, n, fp);
-                }
-                __syncthreads();
-            }
-        }
-        if (k == 0) {
-            // moments (Eq. DiscrAvr) in double; sums over c_i in {0, +-1}
-            double J0 = 0.0, J1 = 0.0, J2 = 0.0, K = 0.0;
+        // moments (Eq. DiscrAvr) in double; sums over c_i in {0, +-1}
+        auto trace_moments = [&](double& J0, double& J1, double& J2, double& K) {
+            J0 = J1 = J2 = K = 0.0;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const double v = static_cast<double>(a[i]);
@@ -241,73 +223,116 @@ k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
                 if (Lat<Q>::c(i, 2) == 1) J2 += v; else if (Lat<Q>::c(i, 2) == -1) J2 -= v;
                 if (csq<Q>(i) == 1) K += v; else if (csq<Q>(i) == 2) K += 2.0 * v;
             }
-            const double invT = 1.0 / rk;
+        };
+        // polynomial factor (Eq. WeqAlgo, Appendix), with v = beta0 xi u so that
+        // beta0 e_i.u = c_i.v:
+        //   P_i = alpha1 + alpha5 beta0 |u|^2/2 + alpha2 beta0 xi^2 |c_i|^2 / 2
+        //         + (c_i.v)(alpha3 + alpha4 c_i.v)
+        struct PCoef { C A, B, v0, v1, v2; };
+        auto p_coef = [&](double T, double J0, double J1, double J2, double K, double eps_iso) {
+            const double invT = 1.0 / T;
             const double u0 = p.xi * J0 * invT, u1 = p.xi * J1 * invT, u2 = (D == 3) ? p.xi * J2 * invT : 0.0;
             const double uu = u0 * u0 + u1 * u1 + u2 * u2;
-            double eps = p.half_xi2 * K * invT - 0.5 * uu;
-            if constexpr (kIso) {
-                const double rv = sqrt(rsh[0][lx] * rsh[0][lx] + rsh[1][lx] * rsh[1][lx] + rsh[2][lx] * rsh[2][lx]);
-                eps = fd::iso_energy<D>(p.beta0, 0.5 * (rk + rv), 0.5 * (rk - rv), esh[0][lx], esh[1][lx]);
-            }
-            // polynomial factor (Eq. WeqAlgo, Appendix), with v = beta0 xi u so that
-            // beta0 e_i.u = c_i.v:
-            //   P_i = alpha1 + alpha5 beta0 |u|^2/2 + alpha2 beta0 xi^2 |c_i|^2 / 2
-            //         + (c_i.v)(alpha3 + alpha4 c_i.v)
+            const double eps = kIso ? eps_iso : p.half_xi2 * K * invT - 0.5 * uu;
             const double b = p.beta0 * eps;
-            const C A = static_cast<C>(p.a1_0 + p.a1_b * b + p.a5 * p.beta0 * 0.5 * uu);
-            const C B = static_cast<C>((p.a2_0 + p.a2_b * b) * p.beta0 * p.half_xi2);
-            const C v0 = static_cast<C>(p.beta0 * p.xi * u0);
-            const C v1 = static_cast<C>(p.beta0 * p.xi * u1);
-            const C v2 = static_cast<C>(p.beta0 * p.xi * u2);
+            return PCoef{static_cast<C>(p.a1_0 + p.a1_b * b + p.a5 * p.beta0 * 0.5 * uu),
+                         static_cast<C>((p.a2_0 + p.a2_b * b) * p.beta0 * p.half_xi2),
+                         static_cast<C>(p.beta0 * p.xi * u0), static_cast<C>(p.beta0 * p.xi * u1),
+                         static_cast<C>(p.beta0 * p.xi * u2)};
+        };
+        auto p_of = [&](const PCoef& q, int i) {
             const C a3 = cst<C>(p.a3, p.a3f), a4 = cst<C>(p.a4, p.a4f);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                C cv = C(0);
-                if (Lat<Q>::c(i, 0) == 1) cv += v0; else if (Lat<Q>::c(i, 0) == -1) cv -= v0;
-                if (Lat<Q>::c(i, 1) == 1) cv += v1; else if (Lat<Q>::c(i, 1) == -1) cv -= v1;
-                if (Lat<Q>::c(i, 2) == 1) cv += v2; else if (Lat<Q>::c(i, 2) == -1) cv -= v2;
-                C P = A + cv * (a3 + a4 * cv);
-                if (csq<Q>(i) == 1) P += B; else if (csq<Q>(i) == 2) P += C(2) * B;
-                // positivity: qs holds w_i P_i (the equilibrium of population i is w_i P_i rho, Eq. WeqAlgo)
-                if constexpr (kPos) qs[i][lx] = static_cast<C>(p.w[i]) * P;
-                else qs[i][lx] = omw_of<C>(p, i) * P;
-            }
-        }
-        if constexpr (kPos) {
-            // the largest rate in [0, omega] keeping every population's smaller
-            // eigenvalue at or above min(0, its value): wave k bounds velocities
-            // i = k mod 4, and the cell's rate is the minimum of the four bounds
-            __syncthreads();
-            C (*ab)[Q][BX] = reinterpret_cast<C (*)[Q][BX]>(lds + Q * BX);
-            const C r0 = static_cast<C>(rsh[3][lx]), r1 = static_cast<C>(rsh[0][lx]),
-                    r2 = static_cast<C>(rsh[1][lx]), r3 = static_cast<C>(rsh[2][lx]);
-            const C om = static_cast<C>(p.om);
-            C m = om;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                if ((i & 3) == k) {
-                    const C wPi = qs[i][lx];
-                    m = fmin(m, psd_bound<C>(ab[3][i][lx], ab[0][i][lx], ab[1][i][lx], ab[2][i][lx], wPi * r0,
-                                             wPi * r1, wPi * r2, wPi * r3, om));
-                }
-            }
-            pmin[k][lx] = m;
-        }
-        __syncthreads();
-        // collision (Eq. CollisionStep) of this wave's channel
+            C cv = C(0);
+            if (Lat<Q>::c(i, 0) == 1) cv += q.v0; else if (Lat<Q>::c(i, 0) == -1) cv -= q.v0;
+            if (Lat<Q>::c(i, 1) == 1) cv += q.v1; else if (Lat<Q>::c(i, 1) == -1) cv -= q.v1;
+            if (Lat<Q>::c(i, 2) == 1) cv += q.v2; else if (Lat<Q>::c(i, 2) == -1) cv -= q.v2;
+            C P = q.A + cv * (a3 + a4 * cv);
+            if (csq<Q>(i) == 1) P += q.B; else if (csq<Q>(i) == 2) P += C(2) * q.B;
+            return P;
+        };
         const C r = static_cast<C>(rk);
-        C omm, omc = C(0);
-        if constexpr (kPos) {
-            omc = fmin(fmin(pmin[0][lx], pmin[1][lx]), fmin(pmin[2][lx], pmin[3][lx]));
-            omm = C(1) - omc;
-        } else {
-            omm = cst<C>(p.one_m_om, p.one_m_omf);
-        }
         C S[Q];
+        if constexpr (VAR == 0) {
+            // the trace wave builds q_i = omega w_i P_i for all four channels
+            if (k == 0) {
+                double J0, J1, J2, K;
+                trace_moments(J0, J1, J2, K);
+                const PCoef q = p_coef(rk, J0, J1, J2, K, 0.0);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            if constexpr (kPos) S[i] = omm * a[i] + (omc * qs[i][lx]) * r;
-            else S[i] = omm * a[i] + qs[i][lx] * r;
+                for (int i = 0; i < Q; ++i) qs[i][lx] = omw_of<C>(p, i) * p_of(q, i);
+            }
+            __syncthreads();
+            // collision (Eq. CollisionStep) of this wave's channel
+            const C omm = cst<C>(p.one_m_om, p.one_m_omf);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) S[i] = omm * a[i] + qs[i][lx] * r;
+        } else {
+            // Variants: every wave forms the cell's coefficients of P_i itself from the
+            // trace moments and rho_k shared through LDS, so the only barriers are the
+            // exchange itself, the isothermal inversion and the positivity bound.
+            if (k > 0) rsh[k - 1][lx] = rk;
+            else rsh[3][lx] = rk;
+            if (k == 0) {
+                double J0, J1, J2, K;
+                trace_moments(J0, J1, J2, K);
+                jsh[0][lx] = J0;
+                jsh[1][lx] = J1;
+                jsh[2][lx] = J2;
+                jsh[3][lx] = K;
+            }
+            C (*ab)[Q][BX] = reinterpret_cast<C (*)[Q][BX]>(lds);
+            if constexpr (kPos) {
+                // channel k at ab[k - 1] (Bloch), the trace at ab[3]
+#pragma unroll
+                for (int i = 0; i < Q; ++i) ab[k > 0 ? k - 1 : 3][i][lx] = a[i];
+            }
+            __syncthreads();
+            const double T = rsh[3][lx];
+            double eps_iso = 0.0;
+            if constexpr (kIso) {
+                // isothermal model: the Fermi-Dirac state at beta = beta0 with the
+                // cell's density matrix; its eigen-channels (tr rho +- |rho|)/2 are
+                // inverted by waves 1 (up) and 2 (down) side by side
+                const double rv = sqrt(rsh[0][lx] * rsh[0][lx] + rsh[1][lx] * rsh[1][lx] + rsh[2][lx] * rsh[2][lx]);
+                if (k == 1 || k == 2) {
+                    const double n = 0.5 * (T + (k == 1 ? rv : -rv));
+                    esh[k - 1][lx] = fd::iso_channel<D>(p.beta0, n, fp);
+                }
+                __syncthreads();
+                eps_iso = fd::iso_energy<D>(p.beta0, 0.5 * (T + rv), 0.5 * (T - rv), esh[0][lx], esh[1][lx]);
+            }
+            const PCoef q = p_coef(T, jsh[0][lx], jsh[1][lx], jsh[2][lx], jsh[3][lx], eps_iso);
+            C omm, omc = C(0);
+            if constexpr (kPos) {
+                // the largest rate in [0, omega] keeping every population's smaller
+                // eigenvalue at or above min(0, its value): wave k bounds velocities
+                // i = k mod 4, and the cell's rate is the minimum of the four bounds;
+                // the equilibrium of population i is w_i P_i rho (Eq. WeqAlgo)
+                const C r0 = static_cast<C>(rsh[3][lx]), r1 = static_cast<C>(rsh[0][lx]),
+                        r2 = static_cast<C>(rsh[1][lx]), r3 = static_cast<C>(rsh[2][lx]);
+                const C om = static_cast<C>(p.om);
+                C m = om;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    if ((i & 3) == k) {
+                        const C wPi = static_cast<C>(p.w[i]) * p_of(q, i);
+                        m = fmin(m, psd_bound<C>(ab[3][i][lx], ab[0][i][lx], ab[1][i][lx], ab[2][i][lx], wPi * r0,
+                                                 wPi * r1, wPi * r2, wPi * r3, om));
+                    }
+                }
+                pmin[k][lx] = m;
+                __syncthreads();
+                omc = fmin(fmin(pmin[0][lx], pmin[1][lx]), fmin(pmin[2][lx], pmin[3][lx]));
+                omm = C(1) - omc;
+            } else {
+                omm = cst<C>(p.one_m_om, p.one_m_omf);
+            }
+            // collision (Eq. CollisionStep) of this wave's channel
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if constexpr (kPos) S[i] = omm * a[i] + (omc * (static_cast<C>(p.w[i]) * p_of(q, i))) * r;
+                else S[i] = omm * a[i] + (omw_of<C>(p, i) * p_of(q, i)) * r;
+            }
         }
         if constexpr (MODE == kF32) conserve<Q, C, !kIso>(S, a, k);
         if constexpr (FIELD != kFieldNone) {
