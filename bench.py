@@ -14,7 +14,8 @@ roofline fraction, the forward + adjoint time of the differentiable rollout
 forward, one D3Q19 128^3 adjoint step in FP64 and FP32, the magnetic-field
 and variant steps, the launch-bound Riemann run eager and as a HIP graph, the
 library's plain device copy (the achievable-bandwidth reference), the error
-against the stored FP64 oracle run, and the CPU oracle on a bounded sample.
+against the stored FP64 oracle run, and the CPU oracle on the headline
+workload (D3Q19 128^3, a few timed steps) and on the smaller workloads.
 
 With --sweep the line also carries "sweep": every step workload (D2Q9 64^2,
 512^2, 1024^2 shear; D3Q19 64^3, 128^3, 384^3) in each storage type it is
@@ -184,7 +185,8 @@ def sweep(warmup):
 
 
 def measure_adjoint(warmup):
-    """Forward + adjoint rollout (D2Q9 512^2, FP32, 200 steps, K = 20) vs plain FP64 forward."""
+    """Forward + adjoint rollout (D2Q9 512^2, FP32, 200 steps, K = 20) vs the plain FP32 and FP64 forward
+    of the same grid and steps."""
     import torch
     from paper_1309_1656_amd import mlbm, synthetic
     from paper_1309_1656_amd.rollout import MLBMRollout
@@ -207,14 +209,19 @@ def measure_adjoint(warmup):
 
     for _ in range(max(1, warmup // 10)):
         fwd_bwd()
-    t_fb = time_region(fwd_bwd)
+    t_fb = time_region(fwd_bwd, reps=3)
+    W32 = W0.detach().clone()
+    s32 = h32.empty_field()
+    mlbm.mlbm_step(h32, W32, s32, 20)
+    t_f32 = time_region(lambda: mlbm.mlbm_step(h32, W32, s32, steps), reps=3)
     h64 = mlbm.mlbm_create(9, dims_of(shape), tau, 1.0, mlbm.MLBM_STORE_F64)
     W64 = h64.empty_field()
     mlbm.mlbm_init_equilibrium(h64, W64, *device_inputs(h64, f))
     s64 = h64.empty_field()
     mlbm.mlbm_step(h64, W64, s64, 20)
-    t_f64 = time_region(lambda: mlbm.mlbm_step(h64, W64, s64, steps))
+    t_f64 = time_region(lambda: mlbm.mlbm_step(h64, W64, s64, steps), reps=3)
     return {"workload": "d2q9_512^2_f32_200steps_ckpt20", "fwd_adjoint_ms": t_fb,
+            "plain_f32_forward_ms": t_f32, "ratio_to_f32_forward": t_fb / t_f32,
             "plain_f64_forward_ms": t_f64, "ratio_to_f64_forward": t_fb / t_f64,
             "grad_tau": float(tau_t.grad), "grad_W0_norm": float(W0.grad.norm())}
 
@@ -385,25 +392,31 @@ def _oracle_rate(lat, f, tau, min_steps, seconds):
     return int(np.prod(f["T"].shape)) * n / dt / 1e6, n
 
 
-def cpu_baseline(seconds=12.0):
-    """The FP64 oracle on a bounded sample: D3Q19 48^3 cells, steps until ~seconds;
-    also its rate on the smaller step workloads (a few steps each)."""
+def cpu_baseline(seconds=10.0):
+    """The FP64 oracle on the headline workload: D3Q19 128^3, tau 0.8, the same
+    seeded initial state, one warm-up step, then at least 3 timed steps (and at
+    least `seconds`); also its rate on the smaller step workloads (a few steps
+    each) and on a D3Q19 48^3 sample of the same initial-state family."""
     from threadpoolctl import threadpool_limits
     from oracle import qlbm
     from paper_1309_1656_amd import synthetic
-    shape = (48, 48, 48)
+    wl = synthetic.WORKLOADS["d3q19_128"]
+    t0 = time.perf_counter()
     with threadpool_limits(limits=1):    # the oracle is elementwise NumPy; hold any library pool to one thread
-        rate, n = _oracle_rate(qlbm.Lattice(3), synthetic.macroscopic_fields(shape, synthetic.BASE_SEED + 3), 0.8,
-                               3, seconds)
+        rate, n = _oracle_rate(qlbm.Lattice(3), workload_fields("d3q19_128"), wl["tau"], 3, seconds)
         per = {}
         for name, lat_d, steps in (("d2q9_64", 2, 20), ("d2q9_1024_shear", 2, 2), ("d3q19_64", 3, 3)):
-            wl = synthetic.WORKLOADS[name]
-            per[name] = {"MLUPS": _oracle_rate(qlbm.Lattice(lat_d), workload_fields(name), wl["tau"], steps, 0.0)[0],
+            w = synthetic.WORKLOADS[name]
+            per[name] = {"MLUPS": _oracle_rate(qlbm.Lattice(lat_d), workload_fields(name), w["tau"], steps, 0.0)[0],
                          "steps": steps}
+        shape48 = (48, 48, 48)
+        per["d3q19_48_sample"] = {
+            "MLUPS": _oracle_rate(qlbm.Lattice(3), synthetic.macroscopic_fields(shape48, synthetic.BASE_SEED + 3), 0.8,
+                                  3, 0.0)[0], "steps": 3}
     return {"value": rate, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"D3Q19 48^3 cells, {n} steps, tau 0.8, same initial-state family as the workload; "
-                      "NumPy elementwise work, one thread",
-            "per_workload": per,
+            "sample": f"D3Q19 128^3 cells (the headline workload: same seeded initial state, tau {wl['tau']}), "
+                      f"1 warm-up step then {n} timed steps; NumPy elementwise work, one thread",
+            "per_workload": per, "wall_s": time.perf_counter() - t0,
             "host_cpus": os.cpu_count(), "host_cpu_model": _cpu_model()}
 
 
@@ -466,7 +479,8 @@ def main():
         log(f"  eager {extras['launch_bound']['eager_ms']:.3f} ms, graph {extras['launch_bound']['graph_ms']:.3f} ms")
         log("forward + adjoint rollout")
         extras["adjoint"] = measure_adjoint(args.warmup)
-        log(f"  ratio {extras['adjoint']['ratio_to_f64_forward']:.2f}")
+        log(f"  {extras['adjoint']['fwd_adjoint_ms']:.2f} ms: {extras['adjoint']['ratio_to_f32_forward']:.2f}x the FP32 "
+            f"forward, {extras['adjoint']['ratio_to_f64_forward']:.2f}x the FP64 forward")
     if args.workload == "d3q19_128" and (args.adjoint_step or not args.skip_extras):
         log("adjoint step, D3Q19 128^3")
         adj3 = {"workload": "D3Q19 128^3, one mlbm_adjoint_step", "f64_fused_forward_ms": r64["fused_kernel_ms"]}

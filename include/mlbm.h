@@ -480,6 +480,38 @@ int mlbm_adjoint_sweep(mlbm_handle h, const void* W, const void* states, int nst
                        void* lam_tmp, double* dL_domega, void* stream);
 
 /*
+ * mlbm_step_post -- nsteps time steps (Sec. 3.3) that keep only post-collision
+ * states, for checkpointing in post-collision form.  src is the state to
+ * advance from: the pre-collision state W(t) when src_post = 0, or the
+ * post-collision state S(t - 1) of the previous step when src_post = 1 (then
+ * W(t) is its streaming, Eq. TransportStep).  The post-collision state S(t + j)
+ * of step j (j = 0 .. nsteps - 1) is written to field j mod nstates of
+ * `states` (caller-owned device memory, fields one after the other), except
+ * the last one, which goes to dst when dst is not NULL.  No streaming pass
+ * follows: the pre-collision state W(t + nsteps) is mlbm_stream of the last
+ * one.  Passes: one collide-only (src_post = 0) or fused (src_post = 1) pass,
+ * then nsteps - 1 fused passes.  Only kernel launches are enqueued.  The
+ * collision is the handle's (field, variants), except the eigen-channel mode.
+ * Errors: MLBM_EINVAL (null src, src_post not 0 or 1, nsteps < 0, missing
+ * states, nstates < 2 with more than one state kept, src or dst overlapping
+ * the states written or each other, eigen-channel mode), MLBM_EHIP.
+ */
+int mlbm_step_post(mlbm_handle h, const void* src, int src_post, void* dst, void* states, int nstates,
+                   int nsteps, void* stream);
+
+/*
+ * mlbm_adjoint_sweep_post -- mlbm_adjoint_sweep for a segment whose first
+ * state is given in post-collision form: S_prev is the post-collision state of
+ * the step before the segment (read only), so step 0 of the segment gathers
+ * its pre-collision state from S_prev by a pull, as steps 1 .. nsteps - 1
+ * gather theirs from states fields 0 .. nsteps - 2 (the post-collision states
+ * that mlbm_step_post keeps).  Arguments, result and restrictions otherwise
+ * as mlbm_adjoint_sweep.
+ */
+int mlbm_adjoint_sweep_post(mlbm_handle h, const void* S_prev, const void* states, int nsteps, void* lam,
+                            void* lam_tmp, double* dL_domega, void* stream);
+
+/*
  * mlbm_set_f16_reference -- restore the MLBM_STORE_F16DEV reference R (4*Q
  * doubles, [k][i], host) and scale S > 0 saved from mlbm_get_info, so that a
  * saved F16DEV field can be resumed on a new handle.

@@ -681,16 +681,18 @@ static int adjoint_checks(mlbm_handle h, const void* W, const void* states, int 
 
 // Reverse sweep over nsteps adjoint steps: step j reads W_j, gathered from
 // states[j - 1] (post-collision) for j >= 1 and W itself for j = 0.
-static int adjoint_reverse(mlbm_handle h, const void* W, const char* st, int nsteps, void* lam, void* lam_tmp,
-                           double* dL_domega, hipStream_t s) {
+// With w_post, W is the post-collision state of the step before the segment and
+// step 0 gathers its state from W by a pull as well.
+static int adjoint_reverse(mlbm_handle h, const void* W, bool w_post, const char* st, int nsteps, void* lam,
+                           void* lam_tmp, double* dL_domega, hipStream_t s) {
     const int nb = adjoint_blocks(h->kp, h->storage, h->adj);
     size_t fb = 0;
     mlbm_field_bytes(h, &fb);
     void* in = lam;
     void* out = lam_tmp;
     for (int j = nsteps - 1; j >= 0; --j) {
-        const bool pulled = j > 0;
-        const void* wsrc = pulled ? static_cast<const void*>(st + (j - 1) * fb) : W;
+        const bool pulled = j > 0 || w_post;
+        const void* wsrc = j > 0 ? static_cast<const void*>(st + (j - 1) * fb) : W;
         // block partials of dL/domega accumulate over the sweep: one final sum
         HIP_TRY(launch_adjoint(h->Q, h->storage, pulled, wsrc, in, out, h->kp, h->d_partials, j < nsteps - 1, h->adj, s));
         void* t = in;
@@ -714,15 +716,59 @@ int mlbm_adjoint_segment(mlbm_handle h, const void* W, void* states, int nsteps,
     if (nsteps > 1) HIP_TRY(launch_step(StepKind::CollideOnly, h->Q, h->storage, W, st, h->kp, h->fp, h->launch, s));
     for (int j = 1; j < nsteps - 1; ++j)
         HIP_TRY(launch_step(StepKind::Fused, h->Q, h->storage, st + (j - 1) * fb, st + j * fb, h->kp, h->fp, h->launch, s));
-    return adjoint_reverse(h, W, st, nsteps, lam, lam_tmp, dL_domega, s);
+    return adjoint_reverse(h, W, false, st, nsteps, lam, lam_tmp, dL_domega, s);
 }
 
 int mlbm_adjoint_sweep(mlbm_handle h, const void* W, const void* states, int nsteps, void* lam, void* lam_tmp,
                        double* dL_domega, void* stream) {
     if (int e = adjoint_checks(h, W, states, nsteps, lam, lam_tmp)) return e;
     if (nsteps == 0) return ok();
-    return adjoint_reverse(h, W, static_cast<const char*>(states), nsteps, lam, lam_tmp, dL_domega,
+    return adjoint_reverse(h, W, false, static_cast<const char*>(states), nsteps, lam, lam_tmp, dL_domega,
                            as_stream(stream));
+}
+
+int mlbm_adjoint_sweep_post(mlbm_handle h, const void* S_prev, const void* states, int nsteps, void* lam,
+                            void* lam_tmp, double* dL_domega, void* stream) {
+    if (int e = adjoint_checks(h, S_prev, states, nsteps, lam, lam_tmp)) return e;
+    if (nsteps == 0) return ok();
+    return adjoint_reverse(h, S_prev, true, static_cast<const char*>(states), nsteps, lam, lam_tmp, dL_domega,
+                           as_stream(stream));
+}
+
+int mlbm_step_post(mlbm_handle h, const void* src, int src_post, void* dst, void* states, int nstates, int nsteps,
+                   void* stream) {
+    if (int e = check_handle(h)) return e;
+    if (!src) return fail(MLBM_EINVAL, "null src");
+    if (src_post != 0 && src_post != 1) return fail(MLBM_EINVAL, "src_post must be 0 or 1");
+    if (nsteps < 0) return fail(MLBM_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return ok();
+    if (h->eq_mode == MLBM_EQ_EIGEN) return fail(MLBM_EINVAL, "mlbm_step_post does not take the eigen-channel mode");
+    // states written to `states`: all but the last one when dst is given
+    const int m = dst ? nsteps - 1 : nsteps;
+    if (m > 0 && (!states || nstates < 1)) return fail(MLBM_EINVAL, "need states with nstates >= 1");
+    if (m > 1 && nstates < 2) return fail(MLBM_EINVAL, "need nstates >= 2 for more than one kept state (got %d)", nstates);
+    size_t fb = 0;
+    mlbm_field_bytes(h, &fb);
+    const uintptr_t a = reinterpret_cast<uintptr_t>(states);
+    const uintptr_t end = m > 0 ? a + static_cast<uintptr_t>(std::min(m, nstates)) * fb : a;
+    auto in_states = [&](const void* q) {
+        const uintptr_t u = reinterpret_cast<uintptr_t>(q);
+        return m > 0 && u + fb > a && u < end;
+    };
+    auto overlap = [&](const void* p1, const void* p2) {
+        const uintptr_t u = reinterpret_cast<uintptr_t>(p1), v = reinterpret_cast<uintptr_t>(p2);
+        return u < v + fb && v < u + fb;
+    };
+    if (in_states(src)) return fail(MLBM_EINVAL, "src must not overlap the states written");
+    if (dst && (in_states(dst) || overlap(dst, src))) return fail(MLBM_EINVAL, "dst must not overlap src or the states written");
+    hipStream_t s = as_stream(stream);
+    char* st = static_cast<char*>(states);
+    auto out = [&](int j) -> void* { return (dst && j == nsteps - 1) ? dst : st + static_cast<size_t>(j % nstates) * fb; };
+    HIP_TRY(launch_step(src_post ? StepKind::Fused : StepKind::CollideOnly, h->Q, h->storage, src, out(0), h->kp, h->fp,
+                        h->launch, s));
+    for (int j = 1; j < nsteps; ++j)
+        HIP_TRY(launch_step(StepKind::Fused, h->Q, h->storage, out(j - 1), out(j), h->kp, h->fp, h->launch, s));
+    return ok();
 }
 
 int mlbm_device_copy(const void* src, void* dst, size_t bytes, void* stream) {

@@ -371,7 +371,9 @@ k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
 
 // Launch shape (cells per workgroup along x, block order, resident
 // workgroups per CU) when the handle does not fix one, from sweeps on MI355X
-// (fused-pass bandwidth measured through mlbm_step):
+// (fused-pass bandwidth measured through mlbm_step).  D2Q9 grids below 2^20
+// cells, whose fields stay in the caches: 64-cell blocks, one row range per
+// XCD, no cap.  Otherwise:
 //   FP64: 64-cell blocks with at most 2 workgroups per CU for D3Q19 above 64^3
 //     (128^3: 6.00 TB/s against 5.65 uncapped; 384^3 with one row range per
 //     XCD: 5.73 against 5.54 for the best uncapped shape), 3 per CU for
@@ -401,6 +403,14 @@ LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want) {
         c.stores = field_bytes <= 192.0 * 1048576.0 ? 1 : 0;
     }
     const bool big3d = Q == 19 && cells >= 16777216.0 && nx > 64;
+    if (Q == 9 && cells < 1048576.0) {
+        // D2Q9 below 2^20 cells: one contiguous row range per XCD, no cap (512^2: FP64 23.0 against
+        // 24.6 us per pass, FP32 13.1 against 13.7; 64^2 FP64 3.3 against 3.7)
+        if (c.bx == 0) c.bx = 64;
+        if (c.order < 0) c.order = kOrderXcdRange;
+        if (c.cap < 0) c.cap = 0;
+        return c;
+    }
     if (mode == kF64) {
         if (c.bx == 0) c.bx = 64;
         if (c.order < 0) c.order = (Q == 9) ? kOrderInterleave8 : (big3d ? kOrderXcdRange : kOrderNatural);

@@ -26,7 +26,7 @@ EXPORTS = (
     "mlbm_adjoint_step", "mlbm_adjoint_segment", "mlbm_step_states", "mlbm_adjoint_sweep", "mlbm_set_f16_reference", "mlbm_set_launch",
     "mlbm_set_magnetic_field", "mlbm_set_magnetic_field_map", "mlbm_init_chemical", "mlbm_relaxation", "mlbm_set_positivity",
     "mlbm_device_copy", "mlbm_set_store_policy", "mlbm_set_adjoint_launch", "mlbm_moments_noalloc",
-    "mlbm_last_error",
+    "mlbm_step_post", "mlbm_adjoint_sweep_post", "mlbm_last_error",
 )
 
 
@@ -83,6 +83,8 @@ def load_library(path=LIB_PATH):
         "mlbm_adjoint_segment": ([vp, vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_adjoint_sweep": ([vp, vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_step_states": ([vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
+        "mlbm_step_post": ([vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
+        "mlbm_adjoint_sweep_post": ([vp, vp, vp, ctypes.c_int, vp, vp, vp, vp], ctypes.c_int),
         "mlbm_set_f16_reference": ([vp, dp, ctypes.c_double], ctypes.c_int),
         "mlbm_set_launch": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "mlbm_set_magnetic_field": ([vp, dp], ctypes.c_int),
@@ -297,6 +299,18 @@ def mlbm_step_states(h, src, dst, states, nsteps, nstates=None, stream=None):
         _stream_ptr(stream)))
 
 
+def mlbm_step_post(h, src, nsteps, states=None, dst=None, src_post=False, nstates=None, stream=None):
+    """Steps keeping post-collision states only: step j's state goes to field j mod nstates of `states`
+    (default nstates: the number of fields the tensor holds), the last one to dst when given."""
+    kept = nsteps - (1 if dst is not None else 0)
+    if nstates is None:
+        nstates = 0 if states is None else states.numel() // (4 * h.Q * h.info["ncell"])
+    _check(load_library().mlbm_step_post(
+        h.ptr, _field_ptr(h, src, "src"), int(bool(src_post)), None if dst is None else _field_ptr(h, dst, "dst"),
+        _states_ptr(h, states, min(max(kept, 0), nstates), "states"), int(nstates), int(nsteps),
+        _stream_ptr(stream)))
+
+
 def mlbm_collide(h, src, dst, stream=None):
     _check(load_library().mlbm_collide(h.ptr, _field_ptr(h, src, "src"), _field_ptr(h, dst, "dst"),
                                        _stream_ptr(stream)))
@@ -417,6 +431,15 @@ def mlbm_adjoint_sweep(h, W, states, nsteps, lam, lam_tmp, dL_domega=None, strea
     import torch
     _check(load_library().mlbm_adjoint_sweep(
         h.ptr, _field_ptr(h, W, "W"), _states_ptr(h, states, nsteps - 1, "states"), int(nsteps),
+        _field_ptr(h, lam, "lam"), _field_ptr(h, lam_tmp, "lam_tmp"),
+        _dev_ptr(dL_domega, torch.float64, 1, "dL_domega"), _stream_ptr(stream)))
+
+
+def mlbm_adjoint_sweep_post(h, S_prev, states, nsteps, lam, lam_tmp, dL_domega=None, stream=None):
+    """As mlbm_adjoint_sweep, with the segment's first state pulled from the post-collision state S_prev."""
+    import torch
+    _check(load_library().mlbm_adjoint_sweep_post(
+        h.ptr, _field_ptr(h, S_prev, "S_prev"), _states_ptr(h, states, nsteps - 1, "states"), int(nsteps),
         _field_ptr(h, lam, "lam"), _field_ptr(h, lam_tmp, "lam_tmp"),
         _dev_ptr(dL_domega, torch.float64, 1, "dL_domega"), _stream_ptr(stream)))
 

@@ -105,6 +105,17 @@ int main(void) {
     EXPECT(mlbm_set_adjoint_launch(h, MLBM_ADJ_AUTO, 0, MLBM_ORDER_AUTO, 33, -1), MLBM_EINVAL);
     EXPECT(mlbm_set_adjoint_launch(h, MLBM_ADJ_AUTO, 0, MLBM_ORDER_AUTO, -1, 2), MLBM_EINVAL);
     EXPECT(mlbm_set_adjoint_launch(h, MLBM_ADJ_AUTO, 0, MLBM_ORDER_AUTO, -1, -1), MLBM_OK);
+    EXPECT(mlbm_step_post(h, NULL, 0, p2, NULL, 0, 1, NULL), MLBM_EINVAL);                 /* null src */
+    EXPECT(mlbm_step_post(h, p1, 2, p2, NULL, 0, 1, NULL), MLBM_EINVAL);                   /* src_post */
+    EXPECT(mlbm_step_post(h, p1, 0, p2, NULL, 0, -1, NULL), MLBM_EINVAL);                  /* nsteps < 0 */
+    EXPECT(mlbm_step_post(h, p1, 0, p2, NULL, 0, 0, NULL), MLBM_OK);                       /* nothing to do */
+    EXPECT(mlbm_step_post(h, p1, 0, p2, NULL, 0, 2, NULL), MLBM_EINVAL);                   /* missing states */
+    EXPECT(mlbm_step_post(h, p1, 0, NULL, (void*)0x100000, 1, 3, NULL), MLBM_EINVAL);      /* nstates < 2 */
+    EXPECT(mlbm_step_post(h, p1, 0, p1, NULL, 0, 1, NULL), MLBM_EINVAL);                   /* dst = src */
+    EXPECT(mlbm_step_post(h, (void*)0x100000, 0, p2, (void*)0x100000, 2, 3, NULL), MLBM_EINVAL); /* src in states */
+    EXPECT(mlbm_adjoint_sweep_post(h, p1, NULL, 0, p2, (void*)0x3000, NULL, NULL), MLBM_OK);
+    EXPECT(mlbm_adjoint_sweep_post(h, p1, NULL, 2, p2, (void*)0x3000, NULL, NULL), MLBM_EINVAL);
+    EXPECT(mlbm_adjoint_sweep_post(h16, p1, p2, 2, (void*)0x3000, (void*)0x4000, NULL, NULL), MLBM_EINVAL);
     EXPECT(mlbm_moments_noalloc(NULL, p1, NULL, NULL, NULL, NULL, NULL), MLBM_EINVAL);
     EXPECT(mlbm_moments_noalloc(h, NULL, NULL, NULL, NULL, NULL, NULL), MLBM_EINVAL);
     EXPECT(mlbm_device_copy(NULL, p2, 64, NULL), MLBM_EINVAL);

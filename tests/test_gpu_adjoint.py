@@ -233,3 +233,62 @@ def test_rollout_backward_twice():
     loss.backward()
     assert torch.equal(W0.grad, g1)
     assert tau_t.grad.item() == t1.item()
+
+
+@pytest.mark.parametrize("shape", [(37, 70), (13, 9, 11)])
+@pytest.mark.parametrize("n,m", [(1, 1), (2, 3), (5, 4)])
+def test_step_post_equals_step(shape, n, m):
+    """mlbm_step_post keeps the same post-collision states as mlbm_step_states bit for bit; streaming its
+    last state gives mlbm_step's result; continuing from that post-collision state (src_post) for m more
+    steps gives the state after n + m steps."""
+    print(f"step_post {shape} n={n} m={m}", flush=True)
+    f = fields(shape, 47)
+    h = make_handle(shape, tau=0.7)
+    W0 = gpu_init(h, f)
+    ref_states = torch.empty((max(n, 2),) + tuple(W0.shape), dtype=W0.dtype, device="cuda")
+    mlbm.mlbm_step_states(h, W0, h.empty_field(), ref_states, n, nstates=n)
+    states = torch.empty((max(n - 1, 1),) + tuple(W0.shape), dtype=W0.dtype, device="cuda")
+    last = h.empty_field()
+    mlbm.mlbm_step_post(h, W0, n, states=states if n > 1 else None, dst=last, nstates=max(n - 1, 1))
+    for j in range(n - 1):
+        assert torch.equal(states[j], ref_states[j]), j
+    assert torch.equal(last, ref_states[n - 1])
+    after_n = W0.clone()
+    mlbm.mlbm_step(h, after_n, h.empty_field(), n)
+    streamed = h.empty_field()
+    mlbm.mlbm_stream(h, last, streamed)
+    assert torch.equal(streamed, after_n)
+    # continue from the post-collision state, all states into a ring of two
+    ring = torch.empty((2,) + tuple(W0.shape), dtype=W0.dtype, device="cuda")
+    last2 = h.empty_field()
+    mlbm.mlbm_step_post(h, last, m, states=ring, dst=last2, src_post=True, nstates=2)
+    after_nm = W0.clone()
+    mlbm.mlbm_step(h, after_nm, h.empty_field(), n + m)
+    mlbm.mlbm_stream(h, last2, streamed)
+    assert torch.equal(streamed, after_nm)
+
+
+@pytest.mark.parametrize("shape,n", [((37, 70), 5), ((13, 9, 11), 4), ((16, 16), 1)])
+def test_adjoint_sweep_post_equals_sweep(shape, n):
+    """A segment started from the post-collision state before it (mlbm_adjoint_sweep_post) equals the same
+    segment started from its pre-collision state (mlbm_adjoint_sweep), bit for bit."""
+    f = fields(shape, 53)
+    h = make_handle(shape, tau=0.7)
+    W0 = gpu_init(h, f)
+    S_prev = h.empty_field()
+    mlbm.mlbm_step_post(h, W0, 3, states=torch.empty((2,) + tuple(W0.shape), dtype=W0.dtype, device="cuda"),
+                        dst=S_prev, nstates=2)
+    Wa = h.empty_field()
+    mlbm.mlbm_stream(h, S_prev, Wa)                  # pre-collision state at the segment start
+    states = torch.empty((max(n - 1, 1),) + tuple(W0.shape), dtype=W0.dtype, device="cuda")
+    if n > 1:
+        mlbm.mlbm_step_post(h, S_prev, n - 1, states=states, src_post=True, nstates=n - 1)
+    rng = np.random.default_rng(8)
+    lamN = from_pauli(h, rng.standard_normal((4, h.Q) + tuple(shape)))
+    lam_a, lam_b = lamN.clone(), lamN.clone()
+    dom_a = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dom_b = torch.zeros(1, dtype=torch.float64, device="cuda")
+    mlbm.mlbm_adjoint_sweep(h, Wa, states if n > 1 else None, n, lam_a, h.empty_field(), dom_a)
+    mlbm.mlbm_adjoint_sweep_post(h, S_prev, states if n > 1 else None, n, lam_b, h.empty_field(), dom_b)
+    assert torch.equal(lam_a, lam_b)
+    assert dom_a.item() == dom_b.item()
