@@ -198,8 +198,9 @@ k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
         static_assert(VAR == 0 || FIELD == kFieldNone, "variants and the field are exclusive");
         // plain and field kernels: q_i of the trace wave (Q BX values), with a field
         // reused for the exchange of the three Bloch channels (3 Q BX values);
-        // positivity: all four channels of every population (4 Q BX values)
-        __shared__ C lds[(FIELD != kFieldNone ? 3 : (kPos ? 4 : 1)) * Q * BX];
+        // positivity: the other three channels of every population for the wave
+        // that bounds it (3 Q BX values)
+        __shared__ C lds[(FIELD != kFieldNone || kPos ? 3 : 1) * Q * BX];
         __shared__ double rsh[VAR != 0 ? 4 : 1][BX];      // rho_k of the Bloch waves; tr rho
         __shared__ double jsh[VAR != 0 ? 4 : 1][BX];      // the trace wave's j (3 components) and K
         __shared__ double esh[kIso ? 2 : 1][BX];          // isothermal: F_{d/2}(nu) per eigen-channel
@@ -280,11 +281,15 @@ k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
                 jsh[2][lx] = J2;
                 jsh[3][lx] = K;
             }
-            C (*ab)[Q][BX] = reinterpret_cast<C (*)[Q][BX]>(lds);
+            // positivity: wave i mod 4 bounds population i; it holds channel i mod 4 of
+            // it and reads the other three from slot 3 i + (rank of the channel among them)
+            C (*ab)[BX] = reinterpret_cast<C (*)[BX]>(lds);
+            auto slot = [](int i, int kk) { const int b = i & 3; return 3 * i + (kk < b ? kk : kk - 1); };
             if constexpr (kPos) {
-                // channel k at ab[k - 1] (Bloch), the trace at ab[3]
 #pragma unroll
-                for (int i = 0; i < Q; ++i) ab[k > 0 ? k - 1 : 3][i][lx] = a[i];
+                for (int i = 0; i < Q; ++i) {
+                    if ((i & 3) != k) ab[slot(i, k)][lx] = a[i];
+                }
             }
             __syncthreads();
             const double T = rsh[3][lx];
@@ -315,9 +320,11 @@ k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     if ((i & 3) == k) {
+                        C ai[4];
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) ai[kk] = (kk == k) ? a[i] : ab[slot(i, kk)][lx];
                         const C wPi = static_cast<C>(p.w[i]) * p_of(q, i);
-                        m = fmin(m, psd_bound<C>(ab[3][i][lx], ab[0][i][lx], ab[1][i][lx], ab[2][i][lx], wPi * r0,
-                                                 wPi * r1, wPi * r2, wPi * r3, om));
+                        m = fmin(m, psd_bound<C>(ai[0], ai[1], ai[2], ai[3], wPi * r0, wPi * r1, wPi * r2, wPi * r3, om));
                     }
                 }
                 pmin[k][lx] = m;
