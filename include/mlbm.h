@@ -139,7 +139,7 @@ typedef struct {
  * mu0 = 0).  Computes xi, w_i and the Appendix coefficients in double on the
  * host.  Touches no device memory.
  *   lattice  MLBM_D2Q9 or MLBM_D3Q19.   storage  MLBM_STORE_*.
- *   Each dim >= 1 and N < 2^31.
+ *   Each dim >= 1, nx <= 2^29, ny and nz <= 65535, and N < 2^31.
  * Errors: MLBM_EINVAL (null out/dims, bad lattice/storage/dims),
  *         MLBM_EDOMAIN (tau <= 1/2 or not finite, beta0 <= 0 or not finite).
  *         tau > 1/2 keeps |1 - omega| < 1.

@@ -451,17 +451,11 @@ k_adjoint_staged(const typename Store<MODE>::T* __restrict__ Wn, const typename 
     }
 }
 
-// Field write: streaming (non-temporal) or temporal.
-template <bool NT, typename T>
-__device__ __forceinline__ void put(T v, T* ptr) {
-    if constexpr (NT) __builtin_nontemporal_store(v, ptr);
-    else *ptr = v;
-}
-
 // Channel-parallel form: a workgroup covers BX consecutive cells of one row
 // (block_order), four waves per 64 cells, wave group k owning Pauli channel k.
 // Every wave gathers its channel of W_n (at x, or pulled from x - c_i) and of
-// lam_{n+1} (from x + c_i) and writes its channel of lam_n.
+// lam_{n+1} (from x + c_i) and writes its channel of lam_n; with NTS (fields
+// larger than the last-level cache) the loads stream as well as the stores.
 //
 // Everything the collision's adjoint needs from a channel's g_i enters through
 // a few moments: with P_i = A + B |c_i|^2 + (c_i.v)(alpha3 + alpha4 c_i.v)
@@ -536,11 +530,11 @@ k_adjoint_channel(const typename Store<MODE>::T* __restrict__ Wn, const typename
             wx = xp[1 - cx];
         }
         const size_t lrow = static_cast<size_t>(zp[1 + cz]) * ny + yp[1 + cy];
-        wr[i] = Wn[fidx(Q, nx, wrow, k, i, wx)];
-        gr[i] = ln1[fidx(Q, nx, lrow, k, i, xp[1 + cx])];
+        wr[i] = load_row<NTS>(Wn + fidx(Q, nx, wrow, k, i, 0), wx);
+        gr[i] = load_row<NTS>(ln1 + fidx(Q, nx, lrow, k, i, 0), xp[1 + cx]);
     }
 
-    double rk = 0.0;
+    double rk = -0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) rk += static_cast<double>(wr[i]);
 
@@ -552,7 +546,7 @@ k_adjoint_channel(const typename Store<MODE>::T* __restrict__ Wn, const typename
     double u[3] = {0.0, 0.0, 0.0}, uu = 0.0, eps = 0.0, invT = 0.0;
     const double bx = p.beta0 * p.xi;
     if (k == 0) {
-        double J[3] = {0.0, 0.0, 0.0}, K = 0.0;
+        double J[3] = {-0.0, -0.0, -0.0}, K = -0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const double a = static_cast<double>(wr[i]);
@@ -584,11 +578,11 @@ k_adjoint_channel(const typename Store<MODE>::T* __restrict__ Wn, const typename
     const double A = csh[D][lx], B = csh[D + 1][lx];
 
     // moments of this channel's g and sum_i g_i a_i
-    double ga = 0.0, s0 = 0.0, sa = 0.0, sd = 0.0;             // g summed per weight class
-    double m1a[3] = {0.0, 0.0, 0.0}, m1d[3] = {0.0, 0.0, 0.0};  // sum c_i g_i per class
-    double m2a[3] = {0.0, 0.0, 0.0}, m2d[kM2];                  // sum c_ia c_ib g_i per class
+    double ga = -0.0, s0 = -0.0, sa = -0.0, sd = -0.0;             // g summed per weight class
+    double m1a[3] = {-0.0, -0.0, -0.0}, m1d[3] = {-0.0, -0.0, -0.0};  // sum c_i g_i per class
+    double m2a[3] = {-0.0, -0.0, -0.0}, m2d[kM2];                  // sum c_ia c_ib g_i per class
 #pragma unroll
-    for (int n = 0; n < kM2; ++n) m2d[n] = 0.0;
+    for (int n = 0; n < kM2; ++n) m2d[n] = -0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const double g = static_cast<double>(gr[i]);
@@ -620,7 +614,7 @@ k_adjoint_channel(const typename Store<MODE>::T* __restrict__ Wn, const typename
     const double w0 = p.w[0], wa = p.w[1], wd = p.w[2 * D + 1];
     const double m0 = w0 * s0 + wa * sa + wd * sd;
     const double mc = wa * sa + 2.0 * wd * sd;
-    double m1[3] = {0.0, 0.0, 0.0}, M2v[3] = {0.0, 0.0, 0.0}, vM2v = 0.0;
+    double m1[3] = {0.0, 0.0, 0.0}, M2v[3] = {-0.0, -0.0, -0.0}, vM2v = -0.0;
 #pragma unroll
     for (int c = 0; c < D; ++c) m1[c] = wa * m1a[c] + wd * m1d[c];
 #pragma unroll
@@ -631,7 +625,7 @@ k_adjoint_channel(const typename Store<MODE>::T* __restrict__ Wn, const typename
         M2v[ca] += M * v[cb];
         if (ca != cb) M2v[cb] += M * v[ca];
     }
-    double vm1 = 0.0;
+    double vm1 = -0.0;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
         vm1 += v[c] * m1[c];
@@ -656,7 +650,7 @@ k_adjoint_channel(const typename Store<MODE>::T* __restrict__ Wn, const typename
         if (active) {
 #pragma unroll
             for (int i = 0; i < Q; ++i)
-                put<NTS>(static_cast<T>(omm * static_cast<double>(gr[i]) + mix), ln + fidx(Q, nx, row, k, i, x));
+                store_row<NTS>(static_cast<T>(omm * static_cast<double>(gr[i]) + mix), ln + fidx(Q, nx, row, k, i, 0), x);
         }
 #pragma unroll
         for (int c = 0; c < D; ++c) gsh[k - 1][c][lx] = Gu[c];
@@ -678,7 +672,7 @@ k_adjoint_channel(const typename Store<MODE>::T* __restrict__ Wn, const typename
         // lam_n,j0 = (1 - omega) g_j + omega h_0 + omega/T (G_u.(e_j - u) + G_eps (|e_j - u|^2/2 - eps))
         //          = (1 - omega) g_j + K0 + K1.c_j + K2 |c_j|^2
         const double sc = om * invT;
-        double Gu_u = 0.0;
+        double Gu_u = -0.0;
 #pragma unroll
         for (int c = 0; c < D; ++c) Gu_u += Gu[c] * u[c];
         const double K0 = om * h + sc * (Ge * (0.5 * uu - eps) - Gu_u);
@@ -695,12 +689,12 @@ k_adjoint_channel(const typename Store<MODE>::T* __restrict__ Wn, const typename
                     if (Lat<Q>::c(j, c) > 0) t += K1[c];
                     if (Lat<Q>::c(j, c) < 0) t -= K1[c];
                 }
-                put<NTS>(static_cast<T>(omm * static_cast<double>(gr[j]) + t), ln + fidx(Q, nx, row, 0, j, x));
+                store_row<NTS>(static_cast<T>(omm * static_cast<double>(gr[j]) + t), ln + fidx(Q, nx, row, 0, j, 0), x);
             }
         }
     }
     if (k == 0 && lx == 0) {
-        double t = 0.0;
+        double t = -0.0;
 #pragma unroll
         for (int j = 0; j < 4 * kWaves; ++j) t += dsum[j];
         partials[blockIdx.x] = accumulate ? partials[blockIdx.x] + t : t;

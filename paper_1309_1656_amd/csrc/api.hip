@@ -198,6 +198,8 @@ int mlbm_create(mlbm_handle* out, int lattice, const int64_t dims[3], double tau
     if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return fail(MLBM_EINVAL, "dims must be >= 1");
     if (lattice == MLBM_D2Q9 && dims[2] != 1) return fail(MLBM_EINVAL, "D2Q9 needs nz = 1");
     if (dims[1] > 65535 || dims[2] > 65535) return fail(MLBM_EINVAL, "ny and nz must be <= 65535");
+    // the kernels address a cell within its row by a 32-bit byte offset
+    if (dims[0] > (int64_t{1} << 29)) return fail(MLBM_EINVAL, "nx must be <= 2^29");
     const long double n = static_cast<long double>(dims[0]) * dims[1] * dims[2];
     if (n >= 2147483648.0L) return fail(MLBM_EINVAL, "at most 2^31 - 1 cells");
     if (!(std::isfinite(tau) && tau > 0.5)) return fail(MLBM_EDOMAIN, "tau must be finite and > 1/2 (got %g)", tau);

@@ -125,6 +125,35 @@ __host__ __device__ __forceinline__ size_t fidx(int Q, int nx, size_t row, int k
     return ((row * 4 + static_cast<size_t>(k)) * Q + i) * static_cast<size_t>(nx) + x;
 }
 
+// Element x of a field row whose start (one (row, k, i) segment) is the same
+// for the whole wave.  The start stays in scalar registers and each lane adds a
+// 32-bit byte offset, so an access costs no 64-bit address arithmetic per lane
+// (the empty asm keeps the compiler from folding the segments of one cell into
+// a per-lane pointer chain).  x must be non-negative and x * sizeof(T) below
+// 2^32 (rows hold at most 2^31 cells).  NT: streaming access (the line is not
+// kept in the caches), for fields too large to stay in them between passes.
+template <bool NT, typename T>
+__device__ __forceinline__ T load_row(const T* row, int x) {
+    uint64_t a = reinterpret_cast<uint64_t>(row);
+    asm volatile("" : "+s"(a));
+    const auto* q = reinterpret_cast<const __attribute__((address_space(1))) T*>(
+        reinterpret_cast<const __attribute__((address_space(1))) char*>(a) +
+        static_cast<unsigned>(x) * static_cast<unsigned>(sizeof(T)));
+    if constexpr (NT) return __builtin_nontemporal_load(q);
+    else return *q;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ void store_row(T v, T* row, int x) {
+    uint64_t a = reinterpret_cast<uint64_t>(row);
+    asm volatile("" : "+s"(a));
+    auto* q = reinterpret_cast<__attribute__((address_space(1))) T*>(
+        reinterpret_cast<__attribute__((address_space(1))) char*>(a) +
+        static_cast<unsigned>(x) * static_cast<unsigned>(sizeof(T)));
+    if constexpr (NT) __builtin_nontemporal_store(v, q);
+    else *q = v;
+}
+
 // Periodic source coordinates of a pull: index [c + 1] holds (x - c) mod n.
 __device__ __forceinline__ void pull_coords(int x, int n, int stride, int out[3]) {
     out[0] = ((x + 1 == n) ? 0 : x + 1) * stride;   // c = -1

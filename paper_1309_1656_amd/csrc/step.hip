@@ -120,11 +120,26 @@ __device__ __forceinline__ C psd_bound(C a0, C a1, C a2, C a3, C e0, C e1, C e2,
     return best < C(0) ? C(0) : best;
 }
 
-// Field write: streaming (non-temporal) or temporal.
-template <bool NT, typename T>
-__device__ __forceinline__ void store_field(T v, T* ptr) {
-    if constexpr (NT) __builtin_nontemporal_store(v, ptr);
-    else *ptr = v;
+// Field element x of a row segment.  F64 and F32 keep the segment start in
+// scalar registers (load_row / store_row); the FP16-deviation pass indexes per
+// lane, since its decode constants already fill the scalar registers (measured
+// on MI355X at D3Q19 128^3: 146 against 139 us per pass with scalar starts,
+// while F64 gains 1% and F32 3%).  Loads are never streaming here: a
+// streaming load of the source slowed the FP64 pass by 4%.
+template <int MODE, typename T>
+__device__ __forceinline__ T load_field(const T* row, int x) {
+    if constexpr (MODE == kF16Dev) return row[x];
+    else return load_row<false>(row, x);
+}
+
+template <int MODE, bool NT, typename T>
+__device__ __forceinline__ void store_field(T v, T* row, int x) {
+    if constexpr (MODE == kF16Dev) {
+        if constexpr (NT) __builtin_nontemporal_store(v, row + x);
+        else row[x] = v;
+    } else {
+        store_row<NT>(v, row, x);
+    }
 }
 
 // Field pointers of k_step.  Every pass that streams reads and writes distinct
@@ -179,14 +194,14 @@ k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
             srow = static_cast<size_t>(zs[Lat<Q>::c(i, 2) + 1]) * ny + ys[Lat<Q>::c(i, 1) + 1];
             sx = xs[Lat<Q>::c(i, 0) + 1];
         }
-        raw[i] = src[fidx(Q, nx, srow, k, i, sx)];
+        raw[i] = load_field<MODE>(src + fidx(Q, nx, srow, k, i, 0), sx);
     }
 
     if constexpr (!COLL) {
         // Streaming alone: a permutation of the stored values, bit exact.
         if (active) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) store_field<NTS>(raw[i], dst + fidx(Q, nx, row, k, i, x));
+            for (int i = 0; i < Q; ++i) store_field<MODE, NTS>(raw[i], dst + fidx(Q, nx, row, k, i, 0), x);
         }
         return;
     } else {
@@ -371,7 +386,7 @@ k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
         if (active) {
 #pragma unroll
             for (int i = 0; i < Q; ++i)
-                store_field<NTS>(encode<MODE>(S[i], k, i, p), dst + fidx(Q, nx, row, k, i, x));
+                store_field<MODE, NTS>(encode<MODE>(S[i], k, i, p), dst + fidx(Q, nx, row, k, i, 0), x);
         }
     }
 }

@@ -62,6 +62,7 @@ def test_field_bytes():
     ((19, (8, 8, 8), 0.8, 1.0, 3), mlbm.MLBM_EINVAL),     # bad storage
     ((19, (1 << 16, 1 << 10, 1 << 6), 0.8, 1.0, 0), mlbm.MLBM_EINVAL),   # 2^32 cells
     ((19, (8, 70000, 8), 0.8, 1.0, 0), mlbm.MLBM_EINVAL),  # ny too large
+    ((9, ((1 << 29) + 1, 1, 1), 0.8, 1.0, 1), mlbm.MLBM_EINVAL),   # a row beyond 32-bit byte offsets
     ((9, (8, 8, 1), 0.5, 1.0, 0), mlbm.MLBM_EDOMAIN),     # tau = 1/2
     ((9, (8, 8, 1), float("nan"), 1.0, 0), mlbm.MLBM_EDOMAIN),
     ((9, (8, 8, 1), 0.8, 0.0, 0), mlbm.MLBM_EDOMAIN),     # beta0 = 0
