@@ -709,10 +709,11 @@ static dim3 adj_block(int nx) {
 // Automatic launch shape of the adjoint, from sweeps of the kernel alone on
 // MI355X (one adjoint step, D3Q19 128^3 and D2Q9 512^2): the channel form
 // without a magnetic field (cell form: D3Q19 F64 710, F32 346 us; D2Q9 F64
-// 35.7, F32 20.7 us), 64-cell blocks, the step kernels' store rule;
-//   D3Q19: 8-row interleave, FP64 with at most 2 workgroups per CU (642 us,
-//          0.745 of the HBM peak; uncapped 665 us), FP32 uncapped (316 us);
-//   D2Q9: one row range per XCD, uncapped (F64 33.8, F32 20.1 us).
+// 35.7, F32 20.7 us), the step kernels' store rule;
+//   D3Q19: 8-row interleave; FP64 64-cell blocks, at most 2 workgroups per CU
+//          (635 us; 128-cell blocks 654 us), FP32 128-cell blocks uncapped
+//          (307 us; 64-cell blocks 312 us);
+//   D2Q9: 64-cell blocks, one row range per XCD, uncapped (F64 33.8, F32 19.0 us).
 AdjointCfg adjoint_launch(int nx, int ny, int nz, int Q, int mode, int field_mode, AdjointCfg want) {
     AdjointCfg c = want;
     if (field_mode != kFieldNone) c.form = kAdjCell;
@@ -722,7 +723,7 @@ AdjointCfg adjoint_launch(int nx, int ny, int nz, int Q, int mode, int field_mod
         const double field_bytes = 4.0 * Q * cells * (mode == kF64 ? 8 : 4);
         c.lc.stores = field_bytes <= 192.0 * 1048576.0 ? 1 : 0;
     }
-    if (c.lc.bx == 0) c.lc.bx = 64;
+    if (c.lc.bx == 0) c.lc.bx = (Q == 19 && mode == kF32) ? 128 : 64;
     if (c.lc.order < 0) c.lc.order = (Q == 9) ? kOrderXcdRange : kOrderInterleave8;
     if (c.lc.cap < 0) c.lc.cap = (Q == 19 && mode == kF64) ? 2 : 0;
     return c;
