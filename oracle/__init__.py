@@ -29,8 +29,9 @@ Modules
   pauli      conversion between the matrix form and Pauli coefficients
 
 Parity status: every function here is pinned by a CPU test against values the
-paper prints, closed forms, library special functions or invariants, except
-the pointwise accuracy of the polynomial equilibrium against the exact
-Fermi-Dirac function, which the paper shows only in a figure with no number:
-that comparison is "parity unpinned" and is kept as a regression value only.
+paper prints, closed forms, library special functions or invariants.  The
+polynomial equilibrium is pinned by its moments (continuum integration gives
+the exact Fermi-Dirac moments, Sec. 3.2); its pointwise deviation from the
+exact Fermi-Dirac function, which the paper shows only in a figure with no
+number and no stated bound, is asserted only in the ordering the text states.
 """

@@ -9,8 +9,8 @@
   Eq. WeqPoly equal those of the exact Fermi-Dirac function, checked by
   direct numerical integration at the parameters of Fig. 2.
 * Sec. 3.2, discussion of Fig. 2: the deviation grows when beta0 overshoots
-  the physical beta.  The pointwise deviation itself is parity unpinned (the
-  figure carries no numbers); only this ordering is asserted.
+  the physical beta.  The figure carries no numbers and the paper states no
+  pointwise bound, so only this ordering is asserted.
 """
 import numpy as np
 import pytest
@@ -124,7 +124,7 @@ def test_polynomial_equilibrium_has_fd_moments(d, beta0):
 
 @pytest.mark.parametrize("d", [2, 3])
 def test_deviation_grows_when_beta0_overshoots(d):
-    """Ordering only: sup over the p1 axis of |W_eq - W_FD| (parity unpinned values)."""
+    """Ordering only: sup over the p1 axis of |W_eq - W_FD| (the paper prints no values)."""
     u = FIG2["u"][d]
     p = np.zeros((801, d))
     p[:, 0] = np.linspace(-4, 4, 801)
