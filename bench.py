@@ -207,13 +207,13 @@ def measure_adjoint(warmup):
         loss.backward()
         return loss
 
-    for _ in range(max(1, warmup // 10)):
+    for _ in range(max(2, warmup // 5)):
         fwd_bwd()
-    t_fb = time_region(fwd_bwd, reps=3)
+    t_fb = time_region(fwd_bwd, reps=5)
     W32 = W0.detach().clone()
     s32 = h32.empty_field()
     mlbm.mlbm_step(h32, W32, s32, 20)
-    t_f32 = time_region(lambda: mlbm.mlbm_step(h32, W32, s32, steps), reps=3)
+    t_f32 = time_region(lambda: mlbm.mlbm_step(h32, W32, s32, steps), reps=5)
     h64 = mlbm.mlbm_create(9, dims_of(shape), tau, 1.0, mlbm.MLBM_STORE_F64)
     W64 = h64.empty_field()
     mlbm.mlbm_init_equilibrium(h64, W64, *device_inputs(h64, f))
