@@ -418,7 +418,10 @@ int mlbm_set_magnetic_field_map(mlbm_handle h, const double* mu_b);
  * blocks_per_cu caps the workgroups resident on one CU (1..32) by reserving
  * unused LDS: fewer waves in flight means fewer concurrent DRAM streams,
  * which raises the bandwidth the pass reaches; 0 = no cap (hardware limit),
- * -1 = automatic.  mlbm_get_info reports the shape in effect.
+ * -1 = automatic.  The automatic shape depends on the kernel in use too: the
+ * magnetic-field and variant kernels (the variants always in 64-cell blocks)
+ * take their own measured order and cap.  mlbm_get_info reports the shape in
+ * effect for the handle's current collision.
  * Errors: MLBM_EINVAL.
  */
 int mlbm_set_launch(mlbm_handle h, int block_x, int order, int blocks_per_cu);

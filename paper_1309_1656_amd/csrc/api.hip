@@ -286,15 +286,8 @@ int mlbm_get_info(mlbm_handle h, mlbm_info* info) {
     info->a3 = h->kp.a3;
     info->a4 = h->kp.a4;
     info->a5 = h->kp.a5;
-    LaunchCfg lc = step_launch(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz), h->Q,
-                               h->storage, h->launch);
-    // as the launcher applies it: the variant kernels exist for 64-cell blocks,
-    // and the field and variant kernels run without the occupancy cap
-    if (h->kp.variant != 0) lc.bx = 64;
-    if (h->kp.variant != 0 || h->kp.field_mode != kFieldNone) {
-        lc.cap = 0;
-        lc.stores = 0;
-    }
+    const LaunchCfg lc = step_launch(static_cast<int>(h->nx), static_cast<int>(h->ny), static_cast<int>(h->nz), h->Q,
+                                     h->storage, h->kp.variant, h->kp.field_mode, h->launch);
     info->launch_block_x = lc.bx;
     info->launch_order = lc.order;
     info->launch_blocks_per_cu = lc.cap;

@@ -18,7 +18,7 @@ struct LaunchCfg {
     int cap = -1;      // workgroups resident per CU: -1 automatic, 0 hardware limit, > 0 at most that many
     int stores = -1;   // field writes: -1 automatic, 0 streaming (non-temporal), 1 temporal
 };
-LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want);
+LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, int variant, int field_mode, LaunchCfg want);
 
 // Dynamic LDS that holds a kernel (launched with `threads` threads per
 // workgroup) to at most `cap` resident workgroups per CU; 0 for cap <= 0.

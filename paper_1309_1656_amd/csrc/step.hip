@@ -414,10 +414,16 @@ k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
 // 26.0 against 29.9 us, D2Q9 1024^2 FP32 48.7 against 50.6 us.  Streaming:
 // D3Q19 128^3 FP64 (1.27 GB per field) 424 against 445 us, D2Q9 1024^2 FP64
 // (302 MB) 98 against 102 us.
-// The cap and the temporal stores are not applied to the magnetic-field
-// kernels (more LDS) and to the isothermal and positivity kernels (more
-// arithmetic per cell).
-LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want) {
+// The magnetic-field kernels (more LDS) and the isothermal and positivity
+// kernels (more arithmetic per cell) always stream their stores, the variants
+// run in 64-cell blocks, and they take their own order and cap: measured per
+// kind at D3Q19 128^3 FP64 (fused-pass medians of five runs, against the
+// uncapped natural order): isothermal 8-row interleave with 3 workgroups per
+// CU (426 against 451 us), positivity natural order with 3 (429 against
+// 441), both together uncapped (443), uniform field 8-row interleave with 2
+// (426 against 433), per-cell field map 8-row interleave with 3 (437 against
+// 471).  Elsewhere they run uncapped in the plain kernels' order.
+LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, int variant, int field_mode, LaunchCfg want) {
     LaunchCfg c = want;
     const double cells = static_cast<double>(nx) * ny * nz;
     if (c.stores < 0) {
@@ -425,6 +431,26 @@ LaunchCfg step_launch(int nx, int ny, int nz, int Q, int mode, LaunchCfg want) {
         c.stores = field_bytes <= 192.0 * 1048576.0 ? 1 : 0;
     }
     const bool big3d = Q == 19 && cells >= 16777216.0 && nx > 64;
+    if (variant != 0 || field_mode != kFieldNone) {
+        LaunchCfg plain = want;
+        plain.order = -1;
+        plain = step_launch(nx, ny, nz, Q, mode, 0, kFieldNone, plain);
+        if (variant != 0) c.bx = 64;                    // the variant kernels exist for 64-cell blocks only
+        else if (c.bx == 0) c.bx = plain.bx;
+        c.stores = 0;
+        const bool measured = Q == 19 && mode == kF64 && cells > 262144.0 && !big3d;
+        int order = plain.order, cap = 0;
+        if (measured) {
+            if (variant == kVarIso) { order = kOrderInterleave8; cap = 3; }
+            else if (variant == kVarPos) { order = kOrderNatural; cap = 3; }
+            else if (variant == (kVarIso | kVarPos)) { order = kOrderNatural; cap = 0; }
+            else if (field_mode == kFieldUniform) { order = kOrderInterleave8; cap = 2; }
+            else if (field_mode == kFieldMap) { order = kOrderInterleave8; cap = 3; }
+        }
+        if (c.order < 0) c.order = order;
+        if (c.cap < 0) c.cap = cap;
+        return c;
+    }
     if (Q == 9 && cells < 1048576.0) {
         // D2Q9 below 2^20 cells: one contiguous row range per XCD, no cap (512^2: FP64 23.0 against
         // 24.6 us per pass, FP32 13.1 against 13.7; 64^2 FP64 3.3 against 3.7)
@@ -491,21 +517,20 @@ static hipError_t launch(const void* src, void* dst, const KParams& p, const FdP
                          hipStream_t s) {
     using T = typename Store<MODE>::T;
     if constexpr (VAR != 0) c.bx = 64;        // the variants are built for 64-cell blocks only
-    // the cap is measured for the plain kernels; the field and variant kernels
-    // hold more LDS or registers and run uncapped
-    constexpr bool kCapped = VAR == 0 && FIELD == kFieldNone;
-    const bool temporal = kCapped && c.stores == 1;
+    // only the plain kernels write temporally (step_launch streams the others)
+    constexpr bool kPlain = VAR == 0 && FIELD == kFieldNone;
+    const bool temporal = kPlain && c.stores == 1;
     const dim3 grd(static_cast<unsigned>((p.nx + c.bx - 1) / c.bx) * p.ny * p.nz);
     if (c.bx == 64) {
-        const auto fn = temporal ? k_step<Q, MODE, PULL, COLL, 64, FIELD, VAR, !kCapped>
+        const auto fn = temporal ? k_step<Q, MODE, PULL, COLL, 64, FIELD, VAR, !kPlain>
                                  : k_step<Q, MODE, PULL, COLL, 64, FIELD, VAR, true>;
-        const size_t dyn = lds_for_cap(reinterpret_cast<const void*>(fn), 256, kCapped ? c.cap : 0);
+        const size_t dyn = lds_for_cap(reinterpret_cast<const void*>(fn), 256, c.cap);
         hipLaunchKernelGGL(fn, grd, dim3(64, 4), dyn, s, static_cast<const T*>(src), static_cast<T*>(dst), p,
                            c.order, fp);
     } else if constexpr (VAR == 0) {
-        const auto fn = temporal ? k_step<Q, MODE, PULL, COLL, 128, FIELD, 0, !kCapped>
+        const auto fn = temporal ? k_step<Q, MODE, PULL, COLL, 128, FIELD, 0, !kPlain>
                                  : k_step<Q, MODE, PULL, COLL, 128, FIELD, 0, true>;
-        const size_t dyn = lds_for_cap(reinterpret_cast<const void*>(fn), 512, kCapped ? c.cap : 0);
+        const size_t dyn = lds_for_cap(reinterpret_cast<const void*>(fn), 512, c.cap);
         hipLaunchKernelGGL(fn, grd, dim3(128, 4), dyn, s, static_cast<const T*>(src), static_cast<T*>(dst), p,
                            c.order, fp);
     }
@@ -537,7 +562,7 @@ static hipError_t dispatch_kind(StepKind kind, const void* src, void* dst, const
 
 hipError_t launch_step(StepKind kind, int Q, int mode, const void* src, void* dst, const KParams& p,
                        const FdParams& fp, LaunchCfg want, hipStream_t s) {
-    const LaunchCfg c = step_launch(p.nx, p.ny, p.nz, Q, mode, want);
+    const LaunchCfg c = step_launch(p.nx, p.ny, p.nz, Q, mode, p.variant, p.field_mode, want);
     if (Q == 9) {
         if (mode == kF64) return dispatch_kind<9, kF64>(kind, src, dst, p, fp, c, s);
         if (mode == kF32) return dispatch_kind<9, kF32>(kind, src, dst, p, fp, c, s);

@@ -122,13 +122,31 @@ def test_set_launch_validation_and_info():
     mlbm.mlbm_set_launch(h, 0, mlbm.MLBM_ORDER_AUTO)
     assert h.info["launch_block_x"] in (64, 128)
     assert h.info["launch_blocks_per_cu"] == 2          # FP64 D3Q19 above 64^3
-    # the field and variant kernels run uncapped; the variants with 64-cell blocks
+    # the field and variant kernels stream and take their own order and cap (measured at D3Q19
+    # 128^3 FP64); the variants always in 64-cell blocks
+    shape_of = lambda i: (i["launch_block_x"], i["launch_order"], i["launch_blocks_per_cu"], i["launch_temporal_stores"])
+    I8, NAT = mlbm.MLBM_ORDER_INTERLEAVE8, mlbm.MLBM_ORDER_NATURAL
     mlbm.mlbm_set_magnetic_field(h, [0.1, 0.0, 0.0])
-    assert h.info["launch_blocks_per_cu"] == 0
+    assert shape_of(h.info) == (64, I8, 2, 0)
     mlbm.mlbm_set_magnetic_field(h, None)
-    mlbm.mlbm_set_launch(h, 128, mlbm.MLBM_ORDER_AUTO, 3)
+    mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_ISOTHERMAL)
+    assert shape_of(h.info) == (64, I8, 3, 0)
     mlbm.mlbm_set_positivity(h, 1)
-    assert h.info["launch_block_x"] == 64 and h.info["launch_blocks_per_cu"] == 0
+    assert shape_of(h.info) == (64, NAT, 0, 0)
+    mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_DIRECT)
+    assert shape_of(h.info) == (64, NAT, 3, 0)
+    mlbm.mlbm_set_launch(h, 128, mlbm.MLBM_ORDER_AUTO, 1)       # an explicit cap holds for them too
+    assert shape_of(h.info) == (64, NAT, 1, 0)
+    mlbm.mlbm_set_positivity(h, 0)
+    assert h.info["launch_block_x"] == 128 and h.info["launch_blocks_per_cu"] == 1
+    # elsewhere (FP32, smaller grids) they run uncapped in the plain kernels' order
+    h32 = mlbm.mlbm_create(19, (128, 128, 128), 0.8, 1.0, mlbm.MLBM_STORE_F32)
+    plain_order = h32.info["launch_order"]
+    mlbm.mlbm_set_positivity(h32, 1)
+    assert shape_of(h32.info) == (64, plain_order, 0, 0)
+    h64 = mlbm.mlbm_create(19, (64, 64, 64), 0.8, 1.0, mlbm.MLBM_STORE_F64)
+    mlbm.mlbm_set_magnetic_field(h64, [0.0, 0.0, 0.1])
+    assert h64.info["launch_blocks_per_cu"] == 0 and h64.info["launch_temporal_stores"] == 0
 
 
 def test_magnetic_field_validation():
