@@ -712,7 +712,9 @@ static dim3 adj_block(int nx) {
 // 35.7, F32 20.7 us), the step kernels' store rule;
 //   D3Q19: 8-row interleave; FP64 64-cell blocks, at most 2 workgroups per CU
 //          (635 us; 128-cell blocks 654 us), FP32 128-cell blocks uncapped
-//          (307 us; 64-cell blocks 312 us);
+//          (307 us; 64-cell blocks 312 us); from 2^24 cells one row range per
+//          XCD instead (384^3: FP64 17.42 against 17.86 ms, FP32 8.56 against
+//          8.83 ms);
 //   D2Q9: 64-cell blocks, one row range per XCD, uncapped (F64 33.8, F32 19.0 us).
 AdjointCfg adjoint_launch(int nx, int ny, int nz, int Q, int mode, int field_mode, AdjointCfg want) {
     AdjointCfg c = want;
@@ -724,7 +726,8 @@ AdjointCfg adjoint_launch(int nx, int ny, int nz, int Q, int mode, int field_mod
         c.lc.stores = field_bytes <= 192.0 * 1048576.0 ? 1 : 0;
     }
     if (c.lc.bx == 0) c.lc.bx = (Q == 19 && mode == kF32) ? 128 : 64;
-    if (c.lc.order < 0) c.lc.order = (Q == 9) ? kOrderXcdRange : kOrderInterleave8;
+    const bool big3d = Q == 19 && cells >= 16777216.0 && nx > 64;
+    if (c.lc.order < 0) c.lc.order = (Q == 9 || big3d) ? kOrderXcdRange : kOrderInterleave8;
     if (c.lc.cap < 0) c.lc.cap = (Q == 19 && mode == kF64) ? 2 : 0;
     return c;
 }

@@ -270,8 +270,9 @@ def test_store_policy():
 
 
 def test_adjoint_launch_shape():
-    """Automatic adjoint shape: the channel form (D3Q19 8-row interleave, FP64 64-cell blocks capped
-    at 2 workgroups per CU, FP32 128-cell blocks; D2Q9 64-cell blocks, per-XCD row ranges) without a
+    """Automatic adjoint shape: the channel form (D3Q19 8-row interleave, per-XCD row ranges from 2^24
+    cells, FP64 64-cell blocks capped at 2 workgroups per CU, FP32 128-cell blocks; D2Q9 64-cell blocks,
+    per-XCD row ranges) without a
     field, the cell form with one; the setter validates its arguments and mlbm_get_info reports the
     shape in effect."""
     h = mlbm.mlbm_create(19, (128, 128, 128), 0.8, 1.0, mlbm.MLBM_STORE_F64)
@@ -283,6 +284,9 @@ def test_adjoint_launch_shape():
     i = h19f32.info
     assert (i["adjoint_form"], i["adjoint_block_x"], i["adjoint_order"], i["adjoint_blocks_per_cu"]) == (
         mlbm.MLBM_ADJ_CHANNEL, 128, mlbm.MLBM_ORDER_INTERLEAVE8, 0)
+    big = mlbm.mlbm_create(19, (384, 384, 384), 0.8, 1.0, mlbm.MLBM_STORE_F64)      # from 2^24 cells: per-XCD rows
+    assert (big.info["adjoint_block_x"], big.info["adjoint_order"], big.info["adjoint_blocks_per_cu"]) == (
+        64, mlbm.MLBM_ORDER_XCD_RANGE, 2)
     h32 = mlbm.mlbm_create(9, (512, 512, 1), 0.8, 1.0, mlbm.MLBM_STORE_F32)
     i = h32.info
     assert (i["adjoint_form"], i["adjoint_block_x"], i["adjoint_order"], i["adjoint_blocks_per_cu"]) == (
