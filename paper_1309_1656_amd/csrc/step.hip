@@ -562,7 +562,10 @@ static hipError_t dispatch_kind(StepKind kind, const void* src, void* dst, const
 
 hipError_t launch_step(StepKind kind, int Q, int mode, const void* src, void* dst, const KParams& p,
                        const FdParams& fp, LaunchCfg want, hipStream_t s) {
-    const LaunchCfg c = step_launch(p.nx, p.ny, p.nz, Q, mode, p.variant, p.field_mode, want);
+    // the stream-only pass runs the plain kernel whatever the collision
+    const bool stream_only = kind == StepKind::StreamOnly;
+    const LaunchCfg c = step_launch(p.nx, p.ny, p.nz, Q, mode, stream_only ? 0 : p.variant,
+                                    stream_only ? static_cast<int>(kFieldNone) : p.field_mode, want);
     if (Q == 9) {
         if (mode == kF64) return dispatch_kind<9, kF64>(kind, src, dst, p, fp, c, s);
         if (mode == kF32) return dispatch_kind<9, kF32>(kind, src, dst, p, fp, c, s);
