@@ -40,3 +40,14 @@ def test_step_workloads_exist():
         assert name in synthetic.WORKLOADS
         assert set(storages) <= set(bench.STORAGE_NAMES)
     assert "d3q19_128" in bench.STEP_WORKLOADS
+
+
+def test_cpu_leg_runs_in_a_spawned_child():
+    """The CPU oracle leg runs in a spawned child process: bench.py must import there without side effects
+    (no GPU use at import), and its functions must reach the child by reference."""
+    import concurrent.futures
+    import multiprocessing
+    sys.path.insert(0, ROOT)
+    import bench
+    with concurrent.futures.ProcessPoolExecutor(max_workers=1, mp_context=multiprocessing.get_context("spawn")) as ex:
+        assert ex.submit(bench._cpu_model).result(timeout=120) == bench._cpu_model()
