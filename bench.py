@@ -210,6 +210,19 @@ def measure_adjoint(warmup):
     for _ in range(max(2, warmup // 5)):
         fwd_bwd()
     t_fb = time_region(fwd_bwd, reps=5)
+    # the two halves of one more run, by events on the current stream
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    W0.grad = None
+    tau_t.grad = None
+    torch.cuda.synchronize()
+    ev[0].record(s)
+    loss = MLBMRollout.apply(W0, tau_t, h32, steps, 20, rt)
+    ev[1].record(s)
+    loss.backward()
+    ev[2].record(s)
+    torch.cuda.synchronize()
+    t_fwd_part, t_bwd_part = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     W32 = W0.detach().clone()
     s32 = h32.empty_field()
     mlbm.mlbm_step(h32, W32, s32, 20)
@@ -221,6 +234,7 @@ def measure_adjoint(warmup):
     mlbm.mlbm_step(h64, W64, s64, 20)
     t_f64 = time_region(lambda: mlbm.mlbm_step(h64, W64, s64, steps), reps=3)
     return {"workload": "d2q9_512^2_f32_200steps_ckpt20", "fwd_adjoint_ms": t_fb,
+            "forward_part_ms": t_fwd_part, "backward_part_ms": t_bwd_part,
             "plain_f32_forward_ms": t_f32, "ratio_to_f32_forward": t_fb / t_f32,
             "plain_f64_forward_ms": t_f64, "ratio_to_f64_forward": t_fb / t_f64,
             "grad_tau": float(tau_t.grad), "grad_W0_norm": float(W0.grad.norm())}
