@@ -534,6 +534,8 @@ k_adjoint_channel(const typename Store<MODE>::T* __restrict__ Wn, const typename
         gr[i] = load_row<NTS>(ln1 + fidx(Q, nx, lrow, k, i, 0), xp[1 + cx]);
     }
 
+    // Sums start at -0.0, the exact additive identity (x + -0.0 == x for every x,
+    // +0.0 included), so the compiler may drop their first addition.
     double rk = -0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) rk += static_cast<double>(wr[i]);
