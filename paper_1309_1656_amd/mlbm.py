@@ -63,6 +63,11 @@ def load_library(path=LIB_PATH):
         return _lib_handle
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run `python -m paper_1309_1656_amd.build`")
+    # torch ships its own HIP runtime under another file name (same soname).
+    # Loaded first, it is the runtime the library binds to; loaded after the
+    # library, it would be a second HIP runtime in the process, and one of the
+    # two then finds no device.  So torch's runtime goes in first.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i64p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
     sig = {

@@ -305,3 +305,27 @@ def test_adjoint_launch_shape():
         with pytest.raises(mlbm.MlbmError) as e:
             mlbm.mlbm_set_adjoint_launch(h, *bad)
         assert e.value.code == mlbm.MLBM_EINVAL
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    """The binding loads the library after torch, so the library binds to the HIP
+    runtime torch already holds (torch ships it under another file name with the
+    same soname).  A second runtime in the process finds no device once the
+    first one has started.  Checked in fresh processes through the mapped files."""
+    import subprocess
+    import sys
+    probe = (
+        "import os, sys\n"
+        "sys.path.insert(0, {root!r})\n"
+        "{first}\n{second}\n"
+        "maps = open('/proc/self/maps').read().split('\\n')\n"
+        "paths = {{l.split()[-1] for l in maps if 'libamdhip64' in l}}\n"
+        "print(len(paths))\n"
+    )
+    lib_first = "from paper_1309_1656_amd import mlbm; mlbm.load_library()"
+    torch_first = "import torch"
+    for first, second in ((lib_first, torch_first), (torch_first, lib_first)):
+        out = subprocess.run([sys.executable, "-c", probe.format(root=ROOT, first=first, second=second)],
+                             capture_output=True, text=True, timeout=300)
+        assert out.returncode == 0, out.stderr
+        assert out.stdout.strip().splitlines()[-1] == "1", (first, out.stdout)
