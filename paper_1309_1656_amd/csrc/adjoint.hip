@@ -717,7 +717,12 @@ static dim3 adj_block(int nx) {
 //          (307 us; 64-cell blocks 312 us); from 2^24 cells one row range per
 //          XCD instead (384^3: FP64 17.42 against 17.86 ms, FP32 8.56 against
 //          8.83 ms);
-//   D2Q9: 64-cell blocks, one row range per XCD, uncapped (F64 33.8, F32 19.0 us).
+//   D2Q9: 64-cell blocks, uncapped; 8-row interleave, which is faster on states
+//         that come from HBM as in a checkpointed reverse sweep (512^2 F32 22.5
+//         against 23.7 us per step, 1024^2 F32 84 against 91 us, F64 162 against
+//         168 us; a 512^2 F32 rollout of 200 steps 9.60 against 9.81 ms), except
+//         F64 below 2^20 cells, one row range per XCD (512^2 sweep 41.4 against
+//         42.4 us per step).
 AdjointCfg adjoint_launch(int nx, int ny, int nz, int Q, int mode, int field_mode, AdjointCfg want) {
     AdjointCfg c = want;
     if (field_mode != kFieldNone) c.form = kAdjCell;
@@ -729,7 +734,8 @@ AdjointCfg adjoint_launch(int nx, int ny, int nz, int Q, int mode, int field_mod
     }
     if (c.lc.bx == 0) c.lc.bx = (Q == 19 && mode == kF32) ? 128 : 64;
     const bool big3d = Q == 19 && cells >= 16777216.0 && nx > 64;
-    if (c.lc.order < 0) c.lc.order = (Q == 9 || big3d) ? kOrderXcdRange : kOrderInterleave8;
+    const bool small_f64_2d = Q == 9 && mode == kF64 && cells < 1048576.0;
+    if (c.lc.order < 0) c.lc.order = (small_f64_2d || big3d) ? kOrderXcdRange : kOrderInterleave8;
     if (c.lc.cap < 0) c.lc.cap = (Q == 19 && mode == kF64) ? 2 : 0;
     return c;
 }

@@ -272,7 +272,7 @@ def test_store_policy():
 def test_adjoint_launch_shape():
     """Automatic adjoint shape: the channel form (D3Q19 8-row interleave, per-XCD row ranges from 2^24
     cells, FP64 64-cell blocks capped at 2 workgroups per CU, FP32 128-cell blocks; D2Q9 64-cell blocks,
-    per-XCD row ranges) without a
+    8-row interleave, per-XCD row ranges for FP64 below 2^20 cells) without a
     field, the cell form with one; the setter validates its arguments and mlbm_get_info reports the
     shape in effect."""
     h = mlbm.mlbm_create(19, (128, 128, 128), 0.8, 1.0, mlbm.MLBM_STORE_F64)
@@ -290,8 +290,12 @@ def test_adjoint_launch_shape():
     h32 = mlbm.mlbm_create(9, (512, 512, 1), 0.8, 1.0, mlbm.MLBM_STORE_F32)
     i = h32.info
     assert (i["adjoint_form"], i["adjoint_block_x"], i["adjoint_order"], i["adjoint_blocks_per_cu"]) == (
-        mlbm.MLBM_ADJ_CHANNEL, 64, mlbm.MLBM_ORDER_XCD_RANGE, 0)
+        mlbm.MLBM_ADJ_CHANNEL, 64, mlbm.MLBM_ORDER_INTERLEAVE8, 0)
     assert i["adjoint_temporal_stores"] == 1
+    h64 = mlbm.mlbm_create(9, (512, 512, 1), 0.8, 1.0, mlbm.MLBM_STORE_F64)    # F64 below 2^20 cells: per-XCD rows
+    assert h64.info["adjoint_order"] == mlbm.MLBM_ORDER_XCD_RANGE
+    h64b = mlbm.mlbm_create(9, (1024, 1024, 1), 0.8, 1.0, mlbm.MLBM_STORE_F64)
+    assert h64b.info["adjoint_order"] == mlbm.MLBM_ORDER_INTERLEAVE8
     mlbm.mlbm_set_adjoint_launch(h, mlbm.MLBM_ADJ_CHANNEL, 128, mlbm.MLBM_ORDER_NATURAL, 3, 1)
     i = h.info
     assert (i["adjoint_block_x"], i["adjoint_order"], i["adjoint_blocks_per_cu"], i["adjoint_temporal_stores"]) == (
