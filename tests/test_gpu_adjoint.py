@@ -292,3 +292,39 @@ def test_adjoint_sweep_post_equals_sweep(shape, n):
     mlbm.mlbm_adjoint_sweep_post(h, S_prev, states if n > 1 else None, n, lam_b, h.empty_field(), dom_b)
     assert torch.equal(lam_a, lam_b)
     assert dom_a.item() == dom_b.item()
+
+
+@pytest.mark.parametrize("shape", [(37, 70), (13, 9, 130)])
+@pytest.mark.parametrize("storage", [mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32])
+def test_adjoint_launch_shapes_give_identical_results(shape, storage):
+    """A 4-step reverse sweep on pulled post-collision states (as in a rollout) under every channel-form
+    shape: block width, XCD order, occupancy cap and store policy only reorder independent cells, so lam is
+    the same bit for bit; dL/domega is summed over other block partials (bounded on the scale of its terms)."""
+    print(f"adjoint launch shapes {shape} storage={storage}", flush=True)
+    f = fields(shape, 59)
+    h = make_handle(shape, tau=0.7, storage=storage)
+    W0 = gpu_init(h, f)
+    S_prev = h.empty_field()
+    mlbm.mlbm_step_post(h, W0, 2, states=torch.empty((2,) + tuple(W0.shape), dtype=W0.dtype, device="cuda"),
+                        dst=S_prev, nstates=2)
+    n = 4
+    states = torch.empty((n - 1,) + tuple(W0.shape), dtype=W0.dtype, device="cuda")
+    mlbm.mlbm_step_post(h, S_prev, n - 1, states=states, src_post=True, nstates=n - 1)
+    lamN = from_pauli(h, np.random.default_rng(10).standard_normal((4, h.Q) + tuple(shape)))
+    scale = n * float(lamN.abs().sum()) * float(S_prev.abs().max())
+    ref = dref = None
+    for stores in (0, 1):
+        for bx in (64, 128):
+            for order in (mlbm.MLBM_ORDER_NATURAL, mlbm.MLBM_ORDER_XCD_RANGE, mlbm.MLBM_ORDER_INTERLEAVE8):
+                for cap in (0, 2):
+                    mlbm.mlbm_set_adjoint_launch(h, mlbm.MLBM_ADJ_CHANNEL, bx, order, cap, stores)
+                    lam = lamN.clone()
+                    dom = torch.zeros(1, dtype=torch.float64, device="cuda")
+                    mlbm.mlbm_adjoint_sweep_post(h, S_prev, states, n, lam, h.empty_field(), dom)
+                    torch.cuda.synchronize()
+                    if ref is None:
+                        ref, dref = lam, dom.item()
+                    else:
+                        assert torch.equal(lam, ref), (stores, bx, order, cap)
+                        assert abs(dom.item() - dref) <= 1e-13 * scale, (stores, bx, order, cap, dom.item(), dref)
+    mlbm.mlbm_set_adjoint_launch(h)
