@@ -127,11 +127,13 @@ def measure_step(shape, seed, tau, storage, steps, warmup, f, field=None, isothe
         mlbm.mlbm_step(h, W, scratch, warmup)
     torch.cuda.synchronize()
     t_all = time_region(lambda: mlbm.mlbm_step(h, W, scratch, steps))
-    # one collide-only + one stream-only pass: the part of mlbm_step that is not the fused pass
-    t_pair = time_region(lambda: mlbm.mlbm_step(h, W, scratch, 1), reps=5)
+    # mlbm_step(n >= 2) is the collide-only pass, n - 2 fused passes and the pass that collides and
+    # pushes into W, so two calls differ by fused passes alone: the fused pass is
+    # (t(steps) - t(2)) / (steps - 2)
+    t_base = time_region(lambda: mlbm.mlbm_step(h, W, scratch, 2), reps=5)
     g1, nneg = mlbm.mlbm_moments(h, W)
     N = int(np.prod(shape))
-    fused_ms = (t_all - t_pair) / max(steps - 1, 1)
+    fused_ms = (t_all - t_base) / (steps - 2)
     bytes_per_cell = 2 * 4 * Q * {0: 8, 1: 4, 2: 2}[storage] + extra_bytes
     achieved = bytes_per_cell * N / (fused_ms * 1e-3) / 1e9
     drift = float(np.max(np.abs(g1 - g0)) / np.max(np.abs(g0)))
@@ -450,6 +452,10 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(spatial sharding by slabs is designed, not built)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 3:
+        print("--steps must be at least 3: the fused pass is timed as the difference of mlbm_step(steps) and "
+              "mlbm_step(2)", file=sys.stderr)
         sys.exit(2)
     # The CPU oracle leg runs in a child process of its own (one host core, started before this
     # process touches the GPU), beside the GPU measurements instead of after them.

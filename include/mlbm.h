@@ -244,9 +244,13 @@ int mlbm_init_chemical(mlbm_handle h, void* W, const double* nu, const double* a
 /*
  * mlbm_step -- advance W by nsteps >= 0 time steps (Sec. 3.3).  W holds the
  * pre-collision state W(t) on entry and W(t + nsteps) on exit.  `scratch` is a
- * second field of the same size, distinct from W, clobbered.  Implementation:
- * one collide-only pass, nsteps - 1 fused pull-stream + collide passes, one
- * stream-only pass, ping-ponging between W and scratch so that no copy is made.
+ * second field of the same size, distinct from W, clobbered.  Implementation,
+ * ping-ponging between W and scratch so that no copy is made: for nsteps >= 2,
+ * one collide-only pass, nsteps - 2 fused pull-stream + collide passes and one
+ * fused pass that writes each collided value where the step's final streaming
+ * sends it (x + c_i), into W: nsteps passes in all.  For nsteps = 1, and in the
+ * eigen-channel mode, one collide-only pass, nsteps - 1 fused passes and one
+ * stream-only pass.  The state is the same bit for bit either way.
  * The collision is the one configured on the handle (equilibrium mode,
  * positivity limit, magnetic field).  Only kernel launches are enqueued (no
  * allocation, memset or synchronisation), so the call can be captured in a

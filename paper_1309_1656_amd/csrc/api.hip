@@ -501,19 +501,31 @@ int mlbm_step(mlbm_handle h, void* W, void* scratch, int nsteps, void* stream) {
         if (eig && kind != StepKind::StreamOnly) return launch_step_eigen(kind, h->Q, a, b, h->kp, h->fp, nullptr, s);
         return launch_step(kind, h->Q, h->storage, a, b, h->kp, h->fp, h->launch, s);
     };
-    // After the collide-only pass and nsteps - 1 fused passes the
-    // post-collision state sits in `scratch`; the stream-only pass then
-    // returns the pre-collision state to W.
-    void* cur = (nsteps % 2 == 0) ? W : scratch;
+    if (nsteps == 1 || eig) {
+        // After the collide-only pass and nsteps - 1 fused passes the
+        // post-collision state sits in `scratch`; the stream-only pass then
+        // returns the pre-collision state to W.
+        void* cur = (nsteps % 2 == 0) ? W : scratch;
+        void* other = (cur == W) ? scratch : W;
+        HIP_TRY(run(StepKind::CollideOnly, W, cur));
+        for (int j = 1; j < nsteps; ++j) {
+            HIP_TRY(run(StepKind::Fused, cur, other));
+            std::swap(cur, other);
+        }
+        HIP_TRY(run(StepKind::StreamOnly, cur, W));
+        return ok();
+    }
+    // nsteps passes: the collide-only pass, nsteps - 2 fused passes, and a last
+    // fused pass whose collided values go where the final streaming sends them,
+    // straight into W.  The state before that last pass is left in `scratch`.
+    void* cur = (nsteps % 2 == 0) ? scratch : W;
     void* other = (cur == W) ? scratch : W;
     HIP_TRY(run(StepKind::CollideOnly, W, cur));
-    for (int j = 1; j < nsteps; ++j) {
+    for (int j = 1; j < nsteps - 1; ++j) {
         HIP_TRY(run(StepKind::Fused, cur, other));
-        void* t = cur;
-        cur = other;
-        other = t;
+        std::swap(cur, other);
     }
-    HIP_TRY(run(StepKind::StreamOnly, cur, W));
+    HIP_TRY(run(StepKind::FusedPush, cur, W));
     return ok();
 }
 

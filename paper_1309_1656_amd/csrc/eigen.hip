@@ -171,6 +171,7 @@ static hipError_t eig_q(StepKind kind, const void* src, void* dst, const KParams
                         hipStream_t s) {
     dim3 blk(p.nx >= 128 ? 128 : 64, p.nx >= 128 ? 2 : 4, 1);
     dim3 grd((p.nx + blk.x - 1) / blk.x, (p.ny + blk.y - 1) / blk.y, p.nz);
+    if (kind == StepKind::FusedPush || kind == StepKind::StreamOnly) return hipErrorInvalidValue;
     if (kind == StepKind::Fused)
         hipLaunchKernelGGL((k_step_eigen<Q, true>), grd, blk, 0, s, static_cast<const double*>(src),
                            static_cast<double*>(dst), p, fp);

@@ -7,7 +7,10 @@
 
 namespace mlbm {
 
-enum class StepKind { Fused, CollideOnly, StreamOnly };
+// Fused: pull-stream then collide; FusedPush: the same, with every collided value
+// written where the next streaming sends it (x + c_i), so that its output is the
+// pre-collision state after the following streaming (src and dst distinct).
+enum class StepKind { Fused, CollideOnly, StreamOnly, FusedPush };
 
 // Launch shape of the step kernels: cells per workgroup along x (64 or 128;
 // 0 = automatic) and block order (-1 = automatic).

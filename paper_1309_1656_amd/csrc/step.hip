@@ -156,7 +156,7 @@ template <typename T> struct FieldPtr<true, T> {
     using out = T* __restrict__;
 };
 
-template <int Q, int MODE, bool PULL, bool COLL, int BX, int FIELD, int VAR, bool NTS = true>
+template <int Q, int MODE, bool PULL, bool COLL, int BX, int FIELD, int VAR, bool NTS = true, bool PUSH = false>
 __global__ void __launch_bounds__(BX * 4)
 k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
        typename FieldPtr<PULL, typename Store<MODE>::T>::out dst, const KParams p, const int order,
@@ -385,8 +385,16 @@ k_step(typename FieldPtr<PULL, typename Store<MODE>::T>::in src,
         }
         if (active) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-                store_field<MODE, NTS>(encode<MODE>(S[i], k, i, p), dst + fidx(Q, nx, row, k, i, 0), x);
+            for (int i = 0; i < Q; ++i) {
+                size_t drow = row;
+                int dx = x;
+                if constexpr (PUSH) {
+                    // the streaming of the step as well (Eq. TransportStep): the value leaves for x + c_i
+                    drow = static_cast<size_t>(zs[1 - Lat<Q>::c(i, 2)]) * ny + ys[1 - Lat<Q>::c(i, 1)];
+                    dx = xs[1 - Lat<Q>::c(i, 0)];
+                }
+                store_field<MODE, NTS>(encode<MODE>(S[i], k, i, p), dst + fidx(Q, nx, drow, k, i, 0), dx);
+            }
         }
     }
 }
@@ -512,7 +520,7 @@ size_t lds_for_cap(const void* fn, int threads, int cap) {
     return dyn;
 }
 
-template <int Q, int MODE, bool PULL, bool COLL, int FIELD, int VAR = 0>
+template <int Q, int MODE, bool PULL, bool COLL, int FIELD, int VAR = 0, bool PUSH = false>
 static hipError_t launch(const void* src, void* dst, const KParams& p, const FdParams& fp, LaunchCfg c,
                          hipStream_t s) {
     using T = typename Store<MODE>::T;
@@ -522,14 +530,14 @@ static hipError_t launch(const void* src, void* dst, const KParams& p, const FdP
     const bool temporal = kPlain && c.stores == 1;
     const dim3 grd(static_cast<unsigned>((p.nx + c.bx - 1) / c.bx) * p.ny * p.nz);
     if (c.bx == 64) {
-        const auto fn = temporal ? k_step<Q, MODE, PULL, COLL, 64, FIELD, VAR, !kPlain>
-                                 : k_step<Q, MODE, PULL, COLL, 64, FIELD, VAR, true>;
+        const auto fn = temporal ? k_step<Q, MODE, PULL, COLL, 64, FIELD, VAR, !kPlain, PUSH>
+                                 : k_step<Q, MODE, PULL, COLL, 64, FIELD, VAR, true, PUSH>;
         const size_t dyn = lds_for_cap(reinterpret_cast<const void*>(fn), 256, c.cap);
         hipLaunchKernelGGL(fn, grd, dim3(64, 4), dyn, s, static_cast<const T*>(src), static_cast<T*>(dst), p,
                            c.order, fp);
     } else if constexpr (VAR == 0) {
-        const auto fn = temporal ? k_step<Q, MODE, PULL, COLL, 128, FIELD, 0, !kPlain>
-                                 : k_step<Q, MODE, PULL, COLL, 128, FIELD, 0, true>;
+        const auto fn = temporal ? k_step<Q, MODE, PULL, COLL, 128, FIELD, 0, !kPlain, PUSH>
+                                 : k_step<Q, MODE, PULL, COLL, 128, FIELD, 0, true, PUSH>;
         const size_t dyn = lds_for_cap(reinterpret_cast<const void*>(fn), 512, c.cap);
         hipLaunchKernelGGL(fn, grd, dim3(128, 4), dyn, s, static_cast<const T*>(src), static_cast<T*>(dst), p,
                            c.order, fp);
@@ -537,16 +545,17 @@ static hipError_t launch(const void* src, void* dst, const KParams& p, const FdP
     return hipGetLastError();
 }
 
-template <int Q, int MODE, bool PULL>
+template <int Q, int MODE, bool PULL, bool PUSH = false>
 static hipError_t launch_coll(const void* src, void* dst, const KParams& p, const FdParams& fp, LaunchCfg c,
                               hipStream_t s) {
-    if (p.variant == kVarIso) return launch<Q, MODE, PULL, true, kFieldNone, kVarIso>(src, dst, p, fp, c, s);
-    if (p.variant == kVarPos) return launch<Q, MODE, PULL, true, kFieldNone, kVarPos>(src, dst, p, fp, c, s);
+    if (p.variant == kVarIso) return launch<Q, MODE, PULL, true, kFieldNone, kVarIso, PUSH>(src, dst, p, fp, c, s);
+    if (p.variant == kVarPos) return launch<Q, MODE, PULL, true, kFieldNone, kVarPos, PUSH>(src, dst, p, fp, c, s);
     if (p.variant == (kVarIso | kVarPos))
-        return launch<Q, MODE, PULL, true, kFieldNone, kVarIso | kVarPos>(src, dst, p, fp, c, s);
-    if (p.field_mode == kFieldUniform) return launch<Q, MODE, PULL, true, kFieldUniform>(src, dst, p, fp, c, s);
-    if (p.field_mode == kFieldMap) return launch<Q, MODE, PULL, true, kFieldMap>(src, dst, p, fp, c, s);
-    return launch<Q, MODE, PULL, true, kFieldNone>(src, dst, p, fp, c, s);
+        return launch<Q, MODE, PULL, true, kFieldNone, kVarIso | kVarPos, PUSH>(src, dst, p, fp, c, s);
+    if (p.field_mode == kFieldUniform)
+        return launch<Q, MODE, PULL, true, kFieldUniform, 0, PUSH>(src, dst, p, fp, c, s);
+    if (p.field_mode == kFieldMap) return launch<Q, MODE, PULL, true, kFieldMap, 0, PUSH>(src, dst, p, fp, c, s);
+    return launch<Q, MODE, PULL, true, kFieldNone, 0, PUSH>(src, dst, p, fp, c, s);
 }
 
 template <int Q, int MODE>
@@ -554,6 +563,7 @@ static hipError_t dispatch_kind(StepKind kind, const void* src, void* dst, const
                                 LaunchCfg c, hipStream_t s) {
     switch (kind) {
         case StepKind::Fused: return launch_coll<Q, MODE, true>(src, dst, p, fp, c, s);
+        case StepKind::FusedPush: return launch_coll<Q, MODE, true, true>(src, dst, p, fp, c, s);
         case StepKind::CollideOnly: return launch_coll<Q, MODE, false>(src, dst, p, fp, c, s);
         case StepKind::StreamOnly: return launch<Q, MODE, true, false, kFieldNone>(src, dst, p, fp, c, s);
     }

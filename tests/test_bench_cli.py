@@ -51,3 +51,9 @@ def test_cpu_leg_runs_in_a_spawned_child():
     import bench
     with concurrent.futures.ProcessPoolExecutor(max_workers=1, mp_context=multiprocessing.get_context("spawn")) as ex:
         assert ex.submit(bench._cpu_model).result(timeout=120) == bench._cpu_model()
+
+
+def test_fewer_than_three_steps_are_refused():
+    r = _run("--steps", "2")
+    assert r.returncode == 2
+    assert "at least 3" in r.stderr
