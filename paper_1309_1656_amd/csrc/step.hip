@@ -25,7 +25,10 @@
 // Template options of k_step: FIELD adds the exact magnetic precession of
 // the Bloch channels after the collision (Sec. 5); VAR selects the isothermal
 // equilibrium (Sec. 3.1) and/or the positivity-limited rate (Sec. 3.3).  Both
-// exchange more data between the waves through LDS and add barriers.
+// exchange more data between the waves through LDS and add barriers.  PUSH
+// (fused pass only) writes each collided value to x + c_i, where the next
+// streaming would take it, so that the last pass of a run of steps leaves the
+// pre-collision state without a separate stream-only pass.
 #include <map>
 #include <mutex>
 #include <utility>
