@@ -267,8 +267,10 @@ int mlbm_step(mlbm_handle h, void* W, void* scratch, int nsteps, void* stream);
  * post-collision state of step j (j = 0 .. nsteps - 1) is written to field
  * j mod nstates, so nstates >= nsteps keeps all of them (the layout
  * mlbm_adjoint_sweep reads) and nstates = 2 is a plain ping-pong.  Passes:
- * one collide-only, nsteps - 1 fused, one stream-only, as in mlbm_step; no
- * copy, except that nsteps = 0 copies src to dst.  Only kernel launches (or
+ * one collide-only, nsteps - 1 fused, one stream-only (every post-collision
+ * state is kept, so the last one is streamed by a pass of its own); the same
+ * values as mlbm_step bit for bit; no copy, except that nsteps = 0 copies src
+ * to dst.  Only kernel launches (or
  * that one copy) are enqueued.
  * Errors: MLBM_EINVAL (null pointers, nsteps < 0, nstates < 1, or < 2 with
  * more than one step, src = dst, src or dst inside the states), MLBM_EHIP.
