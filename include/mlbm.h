@@ -426,8 +426,11 @@ int mlbm_set_magnetic_field_map(mlbm_handle h, const double* mu_b);
  * which raises the bandwidth the pass reaches; 0 = no cap (hardware limit),
  * -1 = automatic.  The automatic shape depends on the kernel in use too: the
  * magnetic-field and variant kernels (the variants always in 64-cell blocks)
- * take their own measured order and cap.  mlbm_get_info reports the shape in
- * effect for the handle's current collision.
+ * take their own measured order and cap, and the last pass of mlbm_step
+ * (which writes pushed) takes 128-cell blocks in natural order when a row has
+ * 65 to 128 cells, so that one workgroup writes a whole row (1 workgroup per
+ * CU for D3Q19 FP64).  mlbm_get_info reports the shape of the other passes
+ * in effect for the handle's current collision.
  * Errors: MLBM_EINVAL.
  */
 int mlbm_set_launch(mlbm_handle h, int block_x, int order, int blocks_per_cu);
