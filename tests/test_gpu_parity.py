@@ -340,20 +340,26 @@ def test_device_copy_is_exact(nbytes):
 
 @pytest.mark.parametrize("shape", [(37, 70), (13, 9, 130), (3, 5, 100)])
 @pytest.mark.parametrize("storage", [mlbm.MLBM_STORE_F64, mlbm.MLBM_STORE_F32, mlbm.MLBM_STORE_F16DEV])
-@pytest.mark.parametrize("feature", [None, "field_map", "isothermal", "positivity"])
+@pytest.mark.parametrize("feature", [None, "field_map", "field_uniform", "isothermal", "positivity", "iso_pos", "eigen"])
 def test_step_equals_single_steps(shape, storage, feature):
     """mlbm_step(n) for n >= 2 ends with a pass that collides and pushes straight into W; mlbm_step(1) is the
     collide-only pass plus the stream-only pass.  n single steps give mlbm_step(n) bit for bit (n odd and even,
     so the collide-only pass runs both in place and out of place), with every collision kind."""
+    if feature == "eigen" and storage != mlbm.MLBM_STORE_F64:
+        pytest.skip("the eigen-channel mode runs on F64 storage only")
     _flush(f"step(n) == n x step(1) {shape} storage={storage} feature={feature}")
     f = fields(shape, 29)
     h = make_handle(shape, storage=storage)
     if feature == "field_map":
         bmap = torch.from_numpy(np.random.default_rng(3).normal(0, 0.05, size=(3,) + tuple(shape))).cuda()
         mlbm.mlbm_set_magnetic_field_map(h, bmap)
-    elif feature == "isothermal":
+    elif feature == "field_uniform":
+        mlbm.mlbm_set_magnetic_field(h, [0.02, -0.03, 0.01])
+    elif feature in ("isothermal", "iso_pos"):
         mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_ISOTHERMAL)
-    elif feature == "positivity":
+    elif feature == "eigen":
+        mlbm.mlbm_set_eq_mode(h, mlbm.MLBM_EQ_EIGEN)
+    if feature in ("positivity", "iso_pos"):
         mlbm.mlbm_set_positivity(h, 1)
     W0 = gpu_init(h, f)
     scratch = h.empty_field()
